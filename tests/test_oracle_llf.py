@@ -1,0 +1,114 @@
+"""Pins for the oracle's Fourier LLF (Eq. (13)-(14)) against the definition of
+LLF (brute force), the series error bound and invariants of the method."""
+import numpy as np
+import pytest
+
+from oracle import fourier_llf_ref as ref
+from paper_2206_04681_amd.synth import synth_image
+
+
+def _img(h, w, seed=0):
+    return synth_image(h, w, 1, seed=seed, n_rect=3, n_disk=2, noise=0.02)[0].astype(np.float64)
+
+
+@pytest.mark.parametrize("h,w,levels,K", [(24, 20, 3, 2), (24, 20, 3, 6), (33, 17, 2, 4),
+                                          (33, 17, 4, 8), (32, 32, 4, 3)])
+def test_fourier_llf_equals_bruteforce_llf_with_truncated_remap(h, w, levels, K):
+    # Every pyramid operator is linear and g = G_l[I]_p is a per-pixel constant,
+    # so Eq. (14) is exactly Eq. (13) run with the remap r_K of Eq. (11).
+    I = _img(h, w, seed=h + w)
+    sigma, m = 0.2, 2.0
+    T = ref.fit_period(sigma, K)
+    got = ref.fourier_llf(I, levels, sigma, m, K, T=T)
+    want = ref.naive_llf(I, levels, lambda X, g: ref.remap_fourier(X, g, sigma, m, K, T))
+    assert ref.max_abs(got, want) < 1e-12
+
+
+def _eps_K(sigma, K, T, R=1.0):
+    x = np.linspace(-R, R, 20001)
+    omega, _, at, _ = ref.fourier_coefficients(sigma, K, T)
+    ser = np.sum(at[:, None] * np.sin(omega[:, None] * x[None, :]), axis=0)
+    return np.max(np.abs(x * np.exp(-x ** 2 / (2 * sigma ** 2)) - ser))
+
+
+def test_error_vs_exact_llf_falls_with_K_within_bound():
+    # |O_K - O| <= 2 * l_max * |m| * eps_K : ||G_l||, ||EXPAND|| <= 1, ||L_l|| <= 2
+    I = _img(24, 20, seed=5)
+    sigma, m, levels = 0.2, 2.0, 3
+    exact = ref.naive_llf(I, levels, lambda X, g: ref.remap_exact(X, g, sigma, m))
+    errs = []
+    for K in (2, 4, 8, 12):
+        T = ref.fit_period(sigma, K)
+        err = ref.max_abs(ref.fourier_llf(I, levels, sigma, m, K, T=T), exact)
+        bound = 2 * (levels - 1) * abs(m) * _eps_K(sigma, K, T)
+        assert err <= bound
+        errs.append(err)
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-9
+
+
+def test_zero_boost_is_identity():
+    I = _img(40, 28, seed=2)
+    np.testing.assert_allclose(ref.fourier_llf(I, 4, 0.2, 0.0, 5), I, atol=1e-13)
+
+
+def test_constant_image_is_fixed():
+    I = np.full((21, 34), 0.42)
+    np.testing.assert_allclose(ref.fourier_llf(I, 4, 0.1, 3.0, 8), 0.42, atol=1e-13)
+
+
+def test_transpose_equivariance():
+    I = _img(26, 19, seed=4)
+    a = ref.fourier_llf(I, 3, 0.15, 2.5, 6)
+    b = ref.fourier_llf(I.T.copy(), 3, 0.15, 2.5, 6)
+    np.testing.assert_allclose(a, b.T, atol=1e-13)
+
+
+def test_flip_equivariance_holds_only_for_symmetric_decimation():
+    # W = 17 -> 9 -> 5 -> 3: the kept (even) samples are mirror-symmetric at every
+    # level, so a horizontal flip commutes with the filter.  For even W it does not,
+    # which pins the decimation phase (even indices kept).
+    I = _img(12, 17, seed=8)
+    a = ref.fourier_llf(I, 4, 0.2, 2.0, 4)
+    b = ref.fourier_llf(I[:, ::-1].copy(), 4, 0.2, 2.0, 4)
+    np.testing.assert_allclose(a, b[:, ::-1], atol=1e-13)
+    I2 = _img(12, 32, seed=8)
+    a2 = ref.fourier_llf(I2, 4, 0.2, 2.0, 4)
+    b2 = ref.fourier_llf(I2[:, ::-1].copy(), 4, 0.2, 2.0, 4)
+    assert ref.max_abs(a2, b2[:, ::-1]) > 1e-3
+
+
+def test_scale_invariance_in_range():
+    # I -> s I with sigma_r -> s sigma_r, R -> s R gives O -> s O
+    I = _img(20, 22, seed=9)
+    s = 255.0
+    a = ref.fourier_llf(I, 3, 0.1, 3.0, 8, R=1.0)
+    b = ref.fourier_llf(s * I, 3, s * 0.1, 3.0, 8, R=s)
+    np.testing.assert_allclose(b / s, a, atol=1e-11)
+
+
+def test_boost_sign_enhances_or_smooths_detail():
+    I = _img(64, 64, seed=11)
+    base = np.std(ref.laplacian_pyramid(I, 2)[0])
+    up = np.std(ref.laplacian_pyramid(ref.fourier_llf(I, 4, 0.2, 2.0, 8), 2)[0])
+    down = np.std(ref.laplacian_pyramid(ref.fourier_llf(I, 4, 0.2, -0.5, 8), 2)[0])
+    assert up > 1.3 * base
+    assert down < 0.95 * base
+
+
+def test_adaptive_with_constant_map_equals_fixed():
+    I = _img(24, 30, seed=12)
+    a = ref.fourier_llf(I, 3, 0.2, 2.0, 4)
+    b = ref.fourier_llf_adaptive(I, 3, 0.2, np.full(I.shape, 2.0), 4)
+    np.testing.assert_allclose(a, b, atol=1e-14)
+
+
+def test_adaptive_equals_bruteforce_with_per_pixel_remap():
+    I = _img(20, 18, seed=13)
+    yy, xx = np.mgrid[0:20, 0:18]
+    mmap = 0.5 + 2.0 * (xx / 17.0)
+    sigma, K = 0.2, 4
+    T = ref.fit_period(sigma, K)
+    got = ref.fourier_llf_adaptive(I, 3, sigma, mmap, K, T=T)
+    want = ref.naive_llf_adaptive(I, 3, lambda X, g, m: ref.remap_fourier(X, g, sigma, m, K, T), mmap)
+    assert ref.max_abs(got, want) < 1e-12
