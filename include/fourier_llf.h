@@ -1,0 +1,157 @@
+/*
+ * fourier_llf.h -- C ABI of libfourier_llf.so, a gfx950 (MI355X) implementation
+ * of the Fourier local Laplacian filter ("Gaussian Fourier Pyramid for Local
+ * Laplacian Filter", Sumiya, Otsuka, Maeda, Fukushima, IEEE SPL).
+ *
+ * What one call computes, per channel of an image I with values in [0, R]
+ * (problem statement of Sec. II-A and Sec. II-C):
+ *   - the period T of Eq. (12) (unless given), omega_k = 2 pi k / T and
+ *     alpha~_k = 2 sigma_r^2 alpha_k omega_k of Eq. (9) and Eq. (11), k = 1..K;
+ *   - the Gaussian pyramid G_l[I] and the 2K Gaussian Fourier pyramids
+ *     G_l[cos(omega_k I)], G_l[sin(omega_k I)] (Eq. (1), Eq. (14) "where" clause);
+ *   - the output Laplacian pyramid L_l[O] by the product-sum of Eq. (14);
+ *   - the collapse O of Eq. (4).
+ * The remap is the detail remap r(i,g) = i + m (i-g) exp(-(i-g)^2 / 2 sigma_r^2)
+ * expanded as in Eq. (11): m > 0 enhances detail, m < 0 smooths it, m = 0 returns I.
+ * The 5-tap binomial [1 4 6 4 1]/16 filter is used for REDUCE and (with gain 4)
+ * for EXPAND; borders are reflect-101; level l+1 has ceil(W_l/2) x ceil(H_l/2)
+ * pixels; the output is not clipped.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named "device" are HIP device pointers owned by the caller; the
+ *     library never allocates device memory.  Scratch comes from the caller's
+ *     workspace (size from fourier_llf_workspace_size).
+ *   - All parameters are validated before anything is enqueued; on a non-OK
+ *     status nothing was launched and fourier_llf_last_error() says why.
+ *   - fourier_llf_run is asynchronous on the caller's stream; results are valid
+ *     once that stream has been synchronised.  A context is not thread-safe; use
+ *     one context per host thread / stream.
+ */
+#ifndef FOURIER_LLF_H
+#define FOURIER_LLF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FLLF_MAX_K 32      /* largest number of Fourier terms K */
+#define FLLF_MAX_LEVELS 16 /* largest |L| (levels, counting the residual level) */
+
+typedef enum {
+  FLLF_OK = 0,
+  FLLF_EINVAL = -1,       /* a parameter is out of range or a pointer is NULL */
+  FLLF_ENOMEM = -2,       /* the workspace passed is smaller than required */
+  FLLF_EDEVICE = -3,      /* a HIP runtime call failed (also reports earlier async faults) */
+  FLLF_EUNSUPPORTED = -4  /* valid request this build does not implement */
+} fllf_status;
+
+/* Storage of the 2K cosine/sine Gaussian Fourier pyramid levels in the
+ * workspace.  Filtering and accumulation are always float32; G_l[I], the output
+ * Laplacian levels and the collapse stay float32 for every storage mode. */
+typedef enum {
+  FLLF_STORE_F32 = 0,
+  FLLF_STORE_F16 = 1,
+  FLLF_STORE_BF16 = 2
+} fllf_storage;
+
+typedef struct fllf_ctx fllf_ctx; /* opaque, host-side state only */
+
+/* One image to filter (Sec. II-A problem statement: image, levels, sigma_r, m, K). */
+typedef struct {
+  const float *in;   /* device; planar channels x height x width float32, dense rows */
+  float *out;        /* device; same layout as in; must not overlap in or the workspace */
+  int32_t width;     /* >= 1 */
+  int32_t height;    /* >= 1 */
+  int32_t channels;  /* >= 1; each channel is filtered independently */
+  int32_t levels;    /* |L| >= 1, counts the residual level;
+                        at most fourier_llf_max_levels(height, width) and FLLF_MAX_LEVELS */
+  int32_t K;         /* number of Fourier terms, 1..FLLF_MAX_K */
+  int32_t flags;     /* must be 0 */
+  double sigma_r;    /* range scale of the remap (Eq. (6)), > 0, same units as the pixels */
+  double m;          /* detail boost of Eq. (6): > 0 enhance, < 0 smooth, 0 identity */
+  double range_R;    /* intensity range R of Eq. (12) (1.0 for [0,1] images), > 0 */
+  double period_T;   /* 0 -> fit by Eq. (12); otherwise the period to use, must be > range_R */
+  const float *m_map;/* optional device map height x width of per-pixel boosts m_p
+                        (pixel-by-pixel form, Sec. III-B); NULL -> the scalar m.
+                        Shared by all channels.  At level l the boost of a level-l
+                        pixel is the Gaussian pyramid value G_l[m_map] there. */
+} fllf_job;
+
+/* Create a context bound to HIP device `device` that stores the Fourier
+ * pyramids as `storage`.  Fails with FLLF_EDEVICE when the device is absent. */
+fllf_status fourier_llf_create(fllf_ctx **out, int device, fllf_storage storage);
+
+/* Bytes of device workspace fourier_llf_run needs for these n jobs (n >= 1).
+ * Equals the resident footprint of the jobs beyond their in/out images. */
+fllf_status fourier_llf_workspace_size(const fllf_ctx *ctx, const fllf_job *jobs, int n,
+                                       size_t *bytes);
+
+/* Filter n jobs (n >= 1, sizes/K/sigma_r may differ) on `hip_stream` (a
+ * hipStream_t; NULL = the legacy default stream).  `workspace` is a device buffer
+ * of at least the size returned by fourier_llf_workspace_size, 256-byte aligned,
+ * owned by the caller and not used by anything else until the stream syncs. */
+fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
+                            size_t ws_bytes, void *hip_stream);
+
+/* Release the context.  NULL-safe.  The caller must have synchronised its streams. */
+void fourier_llf_destroy(fllf_ctx *ctx);
+
+/* Human-readable reason for the last non-OK status returned on this thread
+ * (ctx may be NULL).  The string stays valid until the next call on this thread. */
+const char *fourier_llf_last_error(const fllf_ctx *ctx);
+
+/* ---- kernel timing (benchmarks) ------------------------------------------ */
+
+/* Aggregated device time of one kernel class over the launches recorded since
+ * timing was enabled (or last read). */
+typedef struct {
+  char name[32];      /* kernel class, e.g. "down0", "down", "up0", "up" */
+  int32_t launches;   /* number of launches */
+  double total_ms;    /* summed hipEvent durations */
+  double bytes;       /* summed algorithmic HBM bytes of those launches */
+} fllf_kernel_time;
+
+/* enable != 0: fourier_llf_run brackets every kernel launch with a pair of
+ * hipEvents recorded on the run's stream (adds a few microseconds per launch).
+ * enable == 0: stop recording.  Recorded events are kept until read. */
+fllf_status fourier_llf_timing_enable(fllf_ctx *ctx, int enable);
+
+/* Waits for the recorded events, aggregates them per kernel class into
+ * out[0..max-1] (sorted by total time, largest first), sets *n to the number of
+ * classes and clears the record.  Fails with FLLF_EDEVICE if an event failed. */
+fllf_status fourier_llf_timing_read(fllf_ctx *ctx, fllf_kernel_time *out, int max, int *n);
+
+/* ---- host-only helpers (no device needed) -------------------------------- */
+
+/* Series fit of Eq. (9)-(12) in float64.  If T_in > 0 it is used as the period,
+ * else T = argmin_{T > R} erfc(pi sigma_r (2K+1)/T) + erfc((T-R)/sigma_r).
+ * Writes *T_out and, for k = 1..K, omega[k-1] = 2 pi k / T and
+ * alpha_tilde[k-1] = 2 sigma_r^2 alpha_k omega_k (arrays of length >= K,
+ * either may be NULL). */
+fllf_status fourier_llf_fit(double sigma_r, int K, double range_R, double T_in, double *T_out,
+                            double *omega, double *alpha_tilde);
+
+/* Largest valid level count for an image: 1 + floor(log2(min(height, width))),
+ * capped at FLLF_MAX_LEVELS; 0 for non-positive sizes. */
+int fourier_llf_max_levels(int height, int width);
+
+/* The parameter checks of fourier_llf_run without any device work
+ * (pointers are checked for NULL only). */
+fllf_status fourier_llf_validate(const fllf_job *jobs, int n, fllf_storage storage);
+
+/* Workspace bytes for these jobs with pyramid storage `storage`, without a
+ * context or device (the same number fourier_llf_workspace_size returns).
+ * Used for admission by device-memory footprint. */
+fllf_status fourier_llf_footprint(const fllf_job *jobs, int n, fllf_storage storage, size_t *bytes);
+
+/* Version of this library as major*10000 + minor*100 + patch. */
+int fourier_llf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOURIER_LLF_H */

@@ -1,0 +1,275 @@
+"""Python binding of libfourier_llf.so (argument marshalling only).
+
+Every step of the filter runs in the library's HIP kernels; PyTorch provides
+device memory (inputs, outputs, workspace) and the stream.  Names mirror the C
+ABI declared in ``include/fourier_llf.h``.  There is no CPU fallback: if the
+library is missing or no device is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfourier_llf.so")
+
+FLLF_OK, FLLF_EINVAL, FLLF_ENOMEM, FLLF_EDEVICE, FLLF_EUNSUPPORTED = 0, -1, -2, -3, -4
+FLLF_MAX_K = 32
+FLLF_MAX_LEVELS = 16
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+
+# Every symbol the public header declares (checked by the CPU test suite).
+EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run",
+            "fourier_llf_destroy", "fourier_llf_last_error", "fourier_llf_fit",
+            "fourier_llf_max_levels", "fourier_llf_validate", "fourier_llf_footprint",
+            "fourier_llf_version", "fourier_llf_timing_enable", "fourier_llf_timing_read")
+
+
+class FourierLLFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"fourier_llf status {status}: {message}")
+        self.status = status
+
+
+class FllfKernelTime(ctypes.Structure):
+    """Mirror of ``fllf_kernel_time``."""
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class FllfJob(ctypes.Structure):
+    """Mirror of ``fllf_job``."""
+    _fields_ = [
+        ("in_", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("channels", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
+        ("K", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("sigma_r", ctypes.c_double),
+        ("m", ctypes.c_double),
+        ("range_R", ctypes.c_double),
+        ("period_T", ctypes.c_double),
+        ("m_map", ctypes.c_void_p),
+    ]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_04681_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        jp = ctypes.POINTER(FllfJob)
+        L.fourier_llf_create.argtypes = [ctypes.POINTER(vp), i32, i32]
+        L.fourier_llf_create.restype = i32
+        L.fourier_llf_workspace_size.argtypes = [vp, jp, i32, ctypes.POINTER(sz)]
+        L.fourier_llf_workspace_size.restype = i32
+        L.fourier_llf_run.argtypes = [vp, jp, i32, vp, sz, vp]
+        L.fourier_llf_run.restype = i32
+        L.fourier_llf_destroy.argtypes = [vp]
+        L.fourier_llf_destroy.restype = None
+        L.fourier_llf_last_error.argtypes = [vp]
+        L.fourier_llf_last_error.restype = ctypes.c_char_p
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.fourier_llf_fit.argtypes = [dbl, i32, dbl, dbl, dp, dp, dp]
+        L.fourier_llf_fit.restype = i32
+        L.fourier_llf_max_levels.argtypes = [i32, i32]
+        L.fourier_llf_max_levels.restype = i32
+        L.fourier_llf_validate.argtypes = [jp, i32, i32]
+        L.fourier_llf_validate.restype = i32
+        L.fourier_llf_footprint.argtypes = [jp, i32, i32, ctypes.POINTER(sz)]
+        L.fourier_llf_footprint.restype = i32
+        L.fourier_llf_timing_enable.argtypes = [vp, i32]
+        L.fourier_llf_timing_enable.restype = i32
+        L.fourier_llf_timing_read.argtypes = [vp, ctypes.POINTER(FllfKernelTime), i32, ctypes.POINTER(i32)]
+        L.fourier_llf_timing_read.restype = i32
+        L.fourier_llf_version.argtypes = []
+        L.fourier_llf_version.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def last_error(ctx=None) -> str:
+    s = lib().fourier_llf_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def _check(status: int, ctx=None) -> None:
+    if status != FLLF_OK:
+        raise FourierLLFError(status, last_error(ctx))
+
+
+def fit(sigma_r: float, K: int, R: float = 1.0, T: float = 0.0) -> Tuple[float, np.ndarray, np.ndarray]:
+    """Host float64 series fit: (T, omega_k, alpha~_k) for k = 1..K."""
+    Tout = ctypes.c_double()
+    om = (ctypes.c_double * max(K, 1))()
+    at = (ctypes.c_double * max(K, 1))()
+    _check(lib().fourier_llf_fit(float(sigma_r), int(K), float(R), float(T), ctypes.byref(Tout), om, at))
+    return Tout.value, np.array(om[:K]), np.array(at[:K])
+
+
+def max_levels(height: int, width: int) -> int:
+    return int(lib().fourier_llf_max_levels(int(height), int(width)))
+
+
+def version() -> int:
+    return int(lib().fourier_llf_version())
+
+
+def _job_array(jobs: Sequence[FllfJob]):
+    arr = (FllfJob * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = j
+    return arr
+
+
+def validate(jobs: Sequence[FllfJob], storage: str = "f32") -> int:
+    """Host-only parameter check; returns the status code (0 = OK)."""
+    return int(lib().fourier_llf_validate(_job_array(jobs), len(jobs), STORAGE[storage]))
+
+
+def footprint(jobs: Sequence[FllfJob], storage: str = "f32") -> int:
+    """Workspace bytes for these jobs (host-only; no device needed)."""
+    n = ctypes.c_size_t()
+    _check(lib().fourier_llf_footprint(_job_array(jobs), len(jobs), STORAGE[storage], ctypes.byref(n)))
+    return int(n.value)
+
+
+@dataclass
+class Job:
+    """One image to filter: x is a CUDA float32 tensor (C, H, W) or (H, W)."""
+    x: "object"
+    levels: int
+    sigma_r: float
+    m: float
+    K: int
+    R: float = 1.0
+    T: float = 0.0
+    out: Optional["object"] = None
+    m_map: Optional["object"] = None
+
+
+def make_job(in_ptr: int, out_ptr: int, width: int, height: int, channels: int, levels: int,
+             sigma_r: float, m: float, K: int, R: float = 1.0, T: float = 0.0,
+             m_map_ptr: int = 0) -> FllfJob:
+    j = FllfJob()
+    j.in_ = in_ptr
+    j.out = out_ptr
+    j.width, j.height, j.channels = int(width), int(height), int(channels)
+    j.levels, j.K, j.flags = int(levels), int(K), 0
+    j.sigma_r, j.m, j.range_R, j.period_T = float(sigma_r), float(m), float(R), float(T)
+    j.m_map = m_map_ptr or None
+    return j
+
+
+class FourierLLF:
+    """A library context (one per stream / host thread) with a cached workspace."""
+
+    def __init__(self, storage: str = "f32", device: int = 0):
+        import torch  # memory and streams only
+        if storage not in STORAGE:
+            raise ValueError(f"storage must be one of {sorted(STORAGE)}")
+        self.storage = storage
+        self.device = torch.device("cuda", device)
+        ctx = ctypes.c_void_p()
+        _check(lib().fourier_llf_create(ctypes.byref(ctx), int(device), STORAGE[storage]))
+        self._ctx = ctx
+        self._ws = None
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", None):
+            lib().fourier_llf_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- marshalling ---------------------------------------------------------
+    def _prepare(self, job: Job) -> Tuple[FllfJob, "object"]:
+        import torch
+        x = job.x
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32):
+            raise TypeError("x must be a CUDA float32 tensor")
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous")
+        if x.dim() == 2:
+            C, H, W = 1, x.shape[0], x.shape[1]
+        elif x.dim() == 3:
+            C, H, W = x.shape
+        else:
+            raise ValueError("x must be (H, W) or (C, H, W)")
+        out = job.out if job.out is not None else torch.empty_like(x)
+        if out.shape != x.shape or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor shaped like x")
+        mptr = 0
+        if job.m_map is not None:
+            mm = job.m_map
+            if tuple(mm.shape) != (H, W) or mm.dtype != torch.float32 or not mm.is_contiguous() or not mm.is_cuda:
+                raise ValueError("m_map must be a contiguous CUDA float32 (H, W) tensor")
+            mptr = mm.data_ptr()
+        fj = make_job(x.data_ptr(), out.data_ptr(), W, H, C, job.levels, job.sigma_r, job.m, job.K,
+                      job.R, job.T, mptr)
+        return fj, out
+
+    def workspace_size(self, jobs: Sequence[FllfJob]) -> int:
+        n = ctypes.c_size_t()
+        arr = _job_array(jobs)
+        _check(lib().fourier_llf_workspace_size(self._ctx, arr, len(jobs), ctypes.byref(n)), self._ctx)
+        return int(n.value)
+
+    def workspace(self, nbytes: int):
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def run_jobs(self, fjobs: Sequence[FllfJob], workspace=None, stream=None) -> None:
+        """Enqueue already-marshalled jobs on `stream` (default: torch's current stream)."""
+        import torch
+        arr = _job_array(fjobs)
+        need = self.workspace_size(fjobs)
+        ws = workspace if workspace is not None else self.workspace(need)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().fourier_llf_run(self._ctx, arr, len(fjobs), ws.data_ptr(), ws.numel(), sptr), self._ctx)
+
+    def timing(self, enable: bool) -> None:
+        """Bracket every kernel launch with hipEvents on the run's stream."""
+        _check(lib().fourier_llf_timing_enable(self._ctx, 1 if enable else 0), self._ctx)
+
+    def timing_read(self) -> List[dict]:
+        """Per kernel class: launches, total ms and algorithmic bytes since the last read."""
+        buf = (FllfKernelTime * 16)()
+        n = ctypes.c_int()
+        _check(lib().fourier_llf_timing_read(self._ctx, buf, 16, ctypes.byref(n)), self._ctx)
+        return [dict(name=buf[i].name.decode(), launches=buf[i].launches, total_ms=buf[i].total_ms,
+                     bytes=buf[i].bytes) for i in range(min(n.value, 16))]
+
+    def run(self, x, levels: int, sigma_r: float, m: float, K: int, R: float = 1.0, T: float = 0.0,
+            out=None, m_map=None, stream=None):
+        """Filter one (C, H, W) or (H, W) float32 CUDA tensor; returns the output tensor."""
+        fj, out = self._prepare(Job(x, levels, sigma_r, m, K, R, T, out, m_map))
+        self.run_jobs([fj], stream=stream)
+        return out
+
+    def run_batch(self, jobs: Sequence[Job], stream=None) -> List["object"]:
+        """Filter several images (sizes and parameters may differ) in one call."""
+        prepared = [self._prepare(j) for j in jobs]
+        self.run_jobs([p[0] for p in prepared], stream=stream)
+        return [p[1] for p in prepared]

@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+declared entry point, and its validation, float64 fit and footprint agree with
+the oracle and the documented layout."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fourier_llf_ref as ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fourier_llf.h")
+
+
+@pytest.fixture(scope="session")
+def F():
+    from paper_2206_04681_amd import fllf
+    if not os.path.exists(fllf.LIB_PATH):
+        from paper_2206_04681_amd import build
+        build.build()
+    fllf.lib()
+    return fllf
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fourier_llf_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(F):
+    names = _declared()
+    assert len(names) >= 9
+    raw = ctypes.CDLL(F.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(names) == set(F.EXPORTED)
+
+
+@pytest.mark.parametrize("sigma,K,R", [(0.2, 4, 1.0), (0.1, 8, 1.0), (0.1, 16, 1.0), (0.05, 32, 1.0),
+                                       (0.3, 1, 1.0), (30.0, 10, 256.0)])
+def test_fit_matches_oracle(F, sigma, K, R):
+    T, om, at = F.fit(sigma, K, R)
+    Tr = ref.fit_period(sigma, K, R)
+    assert abs(T - Tr) / Tr < 1e-7
+    omr, _, atr, _ = ref.fourier_coefficients(sigma, K, T)
+    np.testing.assert_allclose(om, omr, rtol=1e-13)
+    np.testing.assert_allclose(at, atr, rtol=1e-12, atol=1e-300)
+
+
+def test_fit_given_period_is_used(F):
+    T, om, _ = F.fit(30.0, 10, 256.0, 405.9)
+    assert T == 405.9 and abs(om[0] - 2 * math.pi / 405.9) < 1e-15
+
+
+@pytest.mark.parametrize("h,w", [(1, 1), (2, 2), (3, 9), (512, 512), (2160, 3840), (33, 4097), (70000, 70000)])
+def test_max_levels(F, h, w):
+    assert F.max_levels(h, w) == min(ref.max_levels(h, w), F.FLLF_MAX_LEVELS)
+
+
+def _job(F, **kw):
+    base = dict(in_ptr=0x1000, out_ptr=0x100000000, width=64, height=48, channels=1, levels=4,
+                sigma_r=0.2, m=2.0, K=4)
+    base.update(kw)
+    return F.make_job(**base)
+
+
+def test_validate_accepts_good_job(F):
+    assert F.validate([_job(F)]) == F.FLLF_OK
+    assert F.validate([_job(F), _job(F, width=3, height=2, levels=2, K=32)], "bf16") == F.FLLF_OK
+
+
+@pytest.mark.parametrize("bad", [
+    dict(in_ptr=0), dict(out_ptr=0), dict(width=0), dict(height=-1), dict(channels=0),
+    dict(levels=0), dict(levels=7), dict(K=0), dict(K=33), dict(sigma_r=0.0), dict(sigma_r=float("nan")),
+    dict(m=float("inf")), dict(R=0.0), dict(T=0.5), dict(T=float("nan")),
+    dict(out_ptr=0x1000 + 64 * 48 * 4 - 4),  # overlaps in
+])
+def test_validate_rejects(F, bad):
+    assert F.validate([_job(F, **bad)]) == F.FLLF_EINVAL
+    assert F.last_error()
+
+
+def test_validate_rejects_bad_storage_and_empty(F):
+    assert F.lib().fourier_llf_validate(F._job_array([_job(F)]), 1, 7) == F.FLLF_EINVAL
+    assert F.lib().fourier_llf_validate(F._job_array([_job(F)]), 0, 0) == F.FLLF_EINVAL
+
+
+def _expected_footprint(w, h, C, L, K, pair_bytes, has_map=False):
+    al = lambda x: (x + 255) // 256 * 256
+    tot = 0
+    for l in range(1, L):
+        wl, hl = -(-w // 2 ** l), -(-h // 2 ** l)
+        n = wl * hl
+        tot += al(4 * n) * C + al(pair_bytes * n) * K * C
+        if l < L - 1:
+            tot += al(4 * n) * C + (al(4 * n) if has_map else 0)
+    return tot
+
+
+@pytest.mark.parametrize("storage,pb", [("f32", 8), ("f16", 4), ("bf16", 4)])
+def test_footprint_matches_layout(F, storage, pb):
+    j = _job(F, width=3840, height=2160, channels=3, levels=8, K=8)
+    assert F.footprint([j], storage) == _expected_footprint(3840, 2160, 3, 8, 8, pb)
+    j2 = _job(F, width=1001, height=777, channels=1, levels=5, K=3, m_map_ptr=0x5000)
+    assert F.footprint([j, j2], storage) == (_expected_footprint(3840, 2160, 3, 8, 8, pb)
+                                             + _expected_footprint(1001, 777, 1, 5, 3, pb, True))
+
+
+def test_footprint_of_4k_rgb_k8(F):
+    # levels >= 1 hold ~N/3 pixels per channel: (4 + 2K*4 + 4) bytes each with float32
+    # pyramids (~0.6 GB), (4 + 2K*2 + 4) with 16-bit ones (~0.33 GB)
+    j = _job(F, width=3840, height=2160, channels=3, levels=8, K=8)
+    assert 0.55e9 < F.footprint([j], "f32") < 0.65e9
+    assert 0.30e9 < F.footprint([j], "f16") < 0.36e9
+
+
+def test_create_without_device_reports_edevice(F):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ctx = ctypes.c_void_p()
+    st = F.lib().fourier_llf_create(ctypes.byref(ctx), 0, 0)
+    assert st == F.FLLF_EDEVICE and not ctx.value
+    assert "device" in F.last_error()
+
+
+def test_product_path_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_2206_04681_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "oracle" not in txt.replace("oracle-free", ""), fn
