@@ -174,9 +174,10 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
     Level &L = p->lv[l];
     L.w = w;
     L.h = h;
+    L.pitch = l == 0 ? w : (int)align_up((size_t)w, 64);
     L.n = (size_t)w * h;
-    const size_t g_plane = align_up(L.n * 4);
-    const size_t cs_plane = align_up(L.n * pair_bytes);
+    const size_t g_plane = align_up((size_t)L.pitch * h * 4);
+    const size_t cs_plane = align_up((size_t)L.pitch * h * pair_bytes);
     L.g_cstride = g_plane / 4;
     L.cs_kstride = cs_plane / pair_bytes;
     L.cs_cstride = L.cs_kstride * job.K;

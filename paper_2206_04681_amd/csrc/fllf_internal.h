@@ -30,6 +30,8 @@ struct Coefs {
 // Geometry and workspace placement of one pyramid level of one job.
 struct Level {
   int w, h;
+  int pitch;         // elements per row: level 0 = the caller's dense rows (w),
+                     // levels >= 1 = w rounded up to 64 (aligned, even: vector loads)
   size_t n;          // w * h
   // byte offsets into the workspace (levels >= 1), per-channel strides in elements
   size_t off_g;      // G_l[I]            float32, channels x plane

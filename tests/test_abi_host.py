@@ -94,7 +94,7 @@ def _expected_footprint(w, h, C, L, K, pair_bytes, has_map=False):
     tot = 0
     for l in range(1, L):
         wl, hl = -(-w // 2 ** l), -(-h // 2 ** l)
-        n = wl * hl
+        n = (wl + 63) // 64 * 64 * hl  # rows padded to 64 elements
         tot += al(4 * n) * C + al(pair_bytes * n) * K * C
         if l < L - 1:
             tot += al(4 * n) * C + (al(4 * n) if has_map else 0)
