@@ -8,6 +8,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -16,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfourier_llf.so")
 ARCH = "gfx950"
 
-SOURCES = ["fllf_host.cpp", "fllf_kernels.hip"]
+SOURCES = ["fllf_host.cpp", "fllf_kernels_f32.hip", "fllf_kernels_f16.hip", "fllf_kernels_bf16.hip"]
 
 # Packed FP32 instructions are disabled for all device code on this target.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -29,23 +30,25 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _compile(cc: str, src: str, obj: str, verbose: bool) -> None:
+    cmd = [cc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
+           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+           "-x", "hip"] + DEVICE_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source into the shared library; returns its path."""
-    objs = []
+    """Compile every source (in parallel) into the shared library; returns its path."""
     tmpdir = os.path.join(HERE, "_build")
     os.makedirs(tmpdir, exist_ok=True)
     cc = hipcc()
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        obj = os.path.join(tmpdir, src + ".o")
-        cmd = [cc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
-               "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
-        cmd += ["-x", "hip"] + DEVICE_FLAGS
-        cmd += ["-c", path, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+    objs = [os.path.join(tmpdir, s + ".o") for s in SOURCES]
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_compile, cc, s, o, verbose) for s, o in zip(SOURCES, objs)]:
+            f.result()
     tmp_lib = LIB + ".tmp"
     link = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp_lib] + objs
     if verbose:

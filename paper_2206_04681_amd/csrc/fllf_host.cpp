@@ -210,6 +210,23 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
   for (int k = 0; k < kMaxK; ++k) p->coefs.at[k] = k < job.K ? (float)at[k] : 0.0f;
 }
 
+const char *const kDownNames[kMaxLevels] = {
+    "down_l0", "down_l1", "down_l2",  "down_l3",  "down_l4",  "down_l5",  "down_l6",  "down_l7",
+    "down_l8", "down_l9", "down_l10", "down_l11", "down_l12", "down_l13", "down_l14", "down_l15"};
+const char *const kUpNames[kMaxLevels] = {"up_l0", "up_l1", "up_l2",  "up_l3",  "up_l4",  "up_l5",
+                                          "up_l6", "up_l7", "up_l8",  "up_l9",  "up_l10", "up_l11",
+                                          "up_l12", "up_l13", "up_l14", "up_l15"};
+
+hipError_t launch_job(const JobPlan &P, fllf_storage storage, char *ws, hipStream_t st, LaunchHook *h) {
+  if (P.levels == 1)
+    return hipMemcpyAsync(P.out, P.in, P.lv[0].n * P.C * sizeof(float), hipMemcpyDeviceToDevice, st);
+  switch (storage) {
+    case FLLF_STORE_F16: return launch_job_f16(P, ws, st, h);
+    case FLLF_STORE_BF16: return launch_job_bf16(P, ws, st, h);
+    default: return launch_job_f32(P, ws, st, h);
+  }
+}
+
 }  // namespace fllf
 
 // ---------------------------------------------------------------------------

@@ -68,8 +68,16 @@ struct LaunchHook {
   virtual void after(hipStream_t s, const char *name, double bytes) = 0;
 };
 
+// Timing names of the per-level kernels ("down_l<l>", "up_l<l>").
+extern const char *const kDownNames[kMaxLevels];
+extern const char *const kUpNames[kMaxLevels];
+
 // Enqueues the whole filter for one planned job on `stream`.
 hipError_t launch_job(const JobPlan &plan, fllf_storage storage, char *ws, hipStream_t stream,
                       LaunchHook *hook);
+// The same per pyramid storage type (one compilation unit each).
+hipError_t launch_job_f32(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook);
+hipError_t launch_job_f16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook);
+hipError_t launch_job_bf16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook);
 
 }  // namespace fllf

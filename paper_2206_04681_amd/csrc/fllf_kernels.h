@@ -1,0 +1,791 @@
+// gfx950 kernels of the Fourier local Laplacian filter (templates; instantiated
+// once per pyramid storage type in fllf_kernels_{f32,f16,bf16}.hip).
+//
+// Per job the filter runs, level by level (all channels of a job in one launch):
+//   down(0):  I -> level 1 of the 2K+1 pyramids G_l[I], C~_{l,k}, S~_{l,k}
+//             (REDUCE of Eq. (1) on every plane).  cos/sin(omega_k I) are formed
+//             in registers and never stored.
+//   down(l):  level l -> level l+1 of the 2K+1 pyramids, l >= 1.  The same pass
+//             evaluates, at every level-l pixel p, the level-l half of Eq. (14):
+//               A_l = G_l - m sum_k at_k (sin(w_k g) C~_{l,k} - cos(w_k g) S~_{l,k}),
+//             g = G_l[I]_p, into the O_l slot (it reads those planes anyway).
+//   up(l):    l = top-1 .. 0:
+//               O_l = A_l + EXPAND(O_{l+1} - G_{l+1})
+//                         + m sum_k at_k (sin(w_k g) EXPAND(C~_{l+1,k}) - cos(w_k g) EXPAND(S~_{l+1,k}))
+//             = L_l[O] of Eq. (14) plus the collapse step of Eq. (4); at level 0,
+//             A_0 = I and the level-0 Fourier terms vanish (first case of Eq. (14)).
+//
+// The Fourier pyramids are stored pre-multiplied by at_k = alpha~_k (REDUCE and
+// EXPAND are linear, so every level carries the same factor); the product-sum
+// then needs no per-term multiply.
+//
+// Memory-bound multi-plane stencils; no LDS and no MFMA.  One wave64 owns a
+// strip of 62 coarse columns (lane t <-> coarse column 62 s + t - 1; lanes 0 and
+// 63 are halo) and streams down a segment of coarse rows.  Horizontal taps come
+// from neighbouring lanes by DPP wave shifts; vertical taps are register
+// running sums.  Each row's loads are issued one row ahead.  All memory access
+// is through buffer resources: plane bases and row offsets live in scalar
+// registers, each lane adds one 32-bit column offset.  Borders: reflect-101 for
+// REDUCE and the matching fold of the coarse grid for EXPAND.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fllf_internal.h"
+
+namespace fllf {
+
+// --------------------------------------------------------------------------
+// Buffer-resource memory access.  A Plane is a uniform 128-bit descriptor of a
+// window starting at `base`; accesses are base + soff (uniform) + voff (lane).
+// Callers keep every offset inside the plane they address.
+// --------------------------------------------------------------------------
+// The scalar offset operand must live in an SGPR.  Every soff passed here is
+// wave-uniform by construction (row and plane offsets), but values that went
+// through VALU arithmetic (integer division) sit in VGPRs; readfirstlane moves
+// them to an SGPR so no per-lane waterfall loop is generated around the access.
+__device__ inline uint32_t sgpr(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+struct Plane {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ explicit Plane(const void *base)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, 0x00020000)) {}
+  __device__ inline float ld1(uint32_t voff, uint32_t soff) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, sgpr(soff), 0));
+  }
+  __device__ inline uint32_t ldu(uint32_t voff, uint32_t soff) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, sgpr(soff), 0);
+  }
+  // 8- and 16-byte loads are written as adjacent dword loads, which the backend
+  // merges into one buffer_load_dwordx2 / dwordx4.  (On this toolchain the
+  // 64- and 128-bit buffer-load builtins return only dword 0 correctly.)
+  __device__ inline float2 ld2(uint32_t voff, uint32_t soff) const {
+    return make_float2(ld1(voff, soff), ld1(voff + 4u, soff));
+  }
+  __device__ inline uint2 ldu2(uint32_t voff, uint32_t soff) const {
+    return make_uint2(ldu(voff, soff), ldu(voff + 4u, soff));
+  }
+  __device__ inline float4 ld4(uint32_t voff, uint32_t soff) const {
+    return make_float4(ld1(voff, soff), ld1(voff + 4u, soff), ld1(voff + 8u, soff), ld1(voff + 12u, soff));
+  }
+  __device__ inline void st1(float x, uint32_t voff, uint32_t soff) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, voff, sgpr(soff), 0);
+  }
+  __device__ inline void stu(uint32_t x, uint32_t voff, uint32_t soff) const {
+    __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, sgpr(soff), 0);
+  }
+  __device__ inline void st2(float2 x, uint32_t voff, uint32_t soff) const {
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    const u2 v = {__builtin_bit_cast(uint32_t, x.x), __builtin_bit_cast(uint32_t, x.y)};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, sgpr(soff), 0);
+  }
+};
+
+// --------------------------------------------------------------------------
+// Storage of the (C, S) pairs.  Arithmetic is always float32.  Loads return
+// the raw stored value (T) so that a prefetch does not wait for the data;
+// cvt() converts at the point of use.
+// --------------------------------------------------------------------------
+template <int S> struct PairStore;
+
+template <> struct PairStore<FLLF_STORE_F32> {
+  using T = float2;
+  static constexpr uint32_t bytes = 8;
+  __device__ static inline float2 cvt(T v) { return v; }
+  __device__ static inline T ld(const Plane &p, uint32_t voff, uint32_t soff) { return p.ld2(voff, soff); }
+  // the pairs of two adjacent pixels (voff 16-byte aligned)
+  __device__ static inline void ld_two(const Plane &p, uint32_t voff, uint32_t soff, T &a, T &b) {
+    const float4 v = p.ld4(voff, soff);
+    a = make_float2(v.x, v.y);
+    b = make_float2(v.z, v.w);
+  }
+  __device__ static inline void st(const Plane &p, float c, float s, uint32_t voff, uint32_t soff) {
+    p.st2(make_float2(c, s), voff, soff);
+  }
+};
+
+template <> struct PairStore<FLLF_STORE_F16> {
+  using T = uint32_t;
+  static constexpr uint32_t bytes = 4;
+  __device__ static inline float2 cvt(T u) {
+    const _Float16 lo = __builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
+    const _Float16 hi = __builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+    return make_float2((float)lo, (float)hi);
+  }
+  __device__ static inline T ld(const Plane &p, uint32_t voff, uint32_t soff) { return p.ldu(voff, soff); }
+  __device__ static inline void ld_two(const Plane &p, uint32_t voff, uint32_t soff, T &a, T &b) {
+    const uint2 v = p.ldu2(voff, soff);
+    a = v.x;
+    b = v.y;
+  }
+  __device__ static inline void st(const Plane &p, float c, float s, uint32_t voff, uint32_t soff) {
+    const uint16_t lo = __builtin_bit_cast(uint16_t, (_Float16)c);
+    const uint16_t hi = __builtin_bit_cast(uint16_t, (_Float16)s);
+    p.stu((uint32_t)lo | ((uint32_t)hi << 16), voff, soff);
+  }
+};
+
+template <> struct PairStore<FLLF_STORE_BF16> {
+  using T = uint32_t;
+  static constexpr uint32_t bytes = 4;
+  __device__ static inline uint32_t to_bf16(float f) {  // round to nearest even; finite inputs
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+  }
+  __device__ static inline float2 cvt(T u) {
+    return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+  }
+  __device__ static inline T ld(const Plane &p, uint32_t voff, uint32_t soff) { return p.ldu(voff, soff); }
+  __device__ static inline void ld_two(const Plane &p, uint32_t voff, uint32_t soff, T &a, T &b) {
+    const uint2 v = p.ldu2(voff, soff);
+    a = v.x;
+    b = v.y;
+  }
+  __device__ static inline void st(const Plane &p, float c, float s, uint32_t voff, uint32_t soff) {
+    p.stu(to_bf16(c) | (to_bf16(s) << 16), voff, soff);
+  }
+};
+
+// --------------------------------------------------------------------------
+// Index helpers
+// --------------------------------------------------------------------------
+// Reflect-101 fold onto [0, n):  ... 2 1 | 0 1 2 ... n-1 | n-2 ...  (any i; no division)
+__device__ inline int reflect(int i, int n) {
+  if (n == 1) return 0;
+  while (i < 0 || i >= n) i = i < 0 ? -i : 2 * n - 2 - i;
+  return i;
+}
+
+// Coarse index feeding EXPAND to a fine axis of nf samples (nc = ceil(nf/2), nf >= 2).
+// Reflect-101 on the zero-inserted fine grid sends the tap left of coarse 0 to
+// coarse 1 and the tap right of coarse nc-1 to nc-1 (nf even) or nc-2 (nf odd).
+// Indices further out only feed lanes whose outputs are discarded: clamp them.
+__device__ inline int cfold(int i, int nc, int nf) {
+  if (i < 0) return nc >= 2 ? 1 : 0;
+  if (i == nc) return (nf & 1) ? nc - 2 : nc - 1;
+  return i > nc ? nc - 1 : i;
+}
+
+// DPP wave shifts: lane t receives lane t-1 (from_left) or lane t+1 (from_right);
+// the lane that has no source gets 0 (bound_ctrl), which only halo lanes see.
+__device__ inline float from_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ inline float from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+
+// sin and cos of 2 pi u, u in revolutions (|u| < 256: the hardware range).
+__device__ inline void sincos2pi(float u, float &s, float &c) {
+  s = __builtin_amdgcn_sinf(u);
+  c = __builtin_amdgcn_cosf(u);
+}
+
+// cos/sin of k theta for k = 1, 2, ... from cos/sin theta by the three-term
+// (Chebyshev) recurrence x_{k+1} = 2 cos(theta) x_k - x_{k-1}: two FMAs per term.
+struct Harmonics {
+  float t, cp, sp, c, s;  // 2 cos(theta); terms k-1 and k
+  __device__ inline void init(float c1, float s1) {
+    t = 2.f * c1;
+    cp = 1.f;
+    sp = 0.f;
+    c = c1;
+    s = s1;
+  }
+  __device__ inline void next() {
+    const float cn = fmaf(t, c, -cp), sn = fmaf(t, s, -sp);
+    cp = c;
+    sp = s;
+    c = cn;
+    s = sn;
+  }
+};
+
+// Unnormalised horizontal REDUCE at the lane's even fine column 2j from its
+// samples v0 (2j), v1 (2j+1) and its neighbours': taps [1 4 6 4 1].
+__device__ inline float hred(float v0, float v1) {
+  return fmaf(6.f, v0, fmaf(4.f, from_left(v1) + v1, from_left(v0) + from_right(v0)));
+}
+
+// Vertical REDUCE as running sums over a stream of horizontally reduced rows.
+// P0 accumulates coarse row i, P1 coarse row i+1.  Weights [1 4 6 4 1]/256
+// carry the 2-D normalisation.  Roles (row of the stream):
+//   0: 2 i0 - 2 (seeds P1 for coarse row i0; P0 is then a dummy)
+//   3: 2 i + 1      4: 2 i + 2  (completes coarse row i, returned in out)
+template <int ROLE>
+__device__ inline void vstep(float h, float &P0, float &P1, float &out) {
+  constexpr float w1 = 1.f / 256.f, w4 = 4.f / 256.f, w6 = 6.f / 256.f;
+  if (ROLE == 0) {
+    P0 = 0.f;
+    P1 = w1 * h;
+  } else if (ROLE == 3) {
+    P0 = fmaf(w4, h, P0);
+    P1 = fmaf(w4, h, P1);
+  } else {
+    out = fmaf(w1, h, P0);
+    P0 = fmaf(w6, h, P1);
+    P1 = w1 * h;
+  }
+}
+
+// Minimum waves per SIMD a kernel is compiled for: 2 (<= 256 VGPRs) up to 8
+// terms; with 16 or 32 terms the pyramid rows need the whole register file.
+constexpr int min_waves_per_simd(int KM) { return KM <= 8 ? 2 : 1; }
+
+// --------------------------------------------------------------------------
+// Kernel arguments
+// --------------------------------------------------------------------------
+struct Geom {
+  int Wf, Hf, Wc, Hc;  // fine and coarse sizes
+  int pf, pc;          // row pitches (elements) of the fine and coarse planes
+  int nstrips, nsegs;  // column strips (62 coarse columns each) and row segments
+  int S;               // coarse rows per segment
+  int C;               // channels
+};
+
+template <typename PT> struct DownArgs {
+  const float *gf; size_t gf_cs;         // G_l (the input I at level 0)
+  const PT *csf; size_t csf_ks, csf_cs;  // level-l pairs (l >= 1)
+  const float *mf;                       // level-l boost plane (m_map at level 0)
+  float *gc; size_t gc_cs;               // G_{l+1}
+  PT *csc; size_t csc_ks, csc_cs;        // level-(l+1) pairs
+  float *mc;                             // level-(l+1) boost plane or null
+  float *af; size_t af_cs;               // A_l (l >= 1), stored in the O_l slot
+  Geom g;
+  Coefs cf;
+};
+
+template <typename PT> struct UpArgs {
+  const float *base; size_t base_cs;     // A_l, or I at level 0 (may alias out)
+  const float *gf; size_t gf_cs;         // G_l, or I at level 0
+  const float *mf;                       // level-l boost plane, or m_map at level 0
+  const float *gc; size_t gc_cs;         // G_{l+1}
+  const float *oc; size_t oc_cs;         // O_{l+1} (null when l+1 is the top level)
+  const PT *csc; size_t csc_ks, csc_cs;  // level-(l+1) pairs
+  float *out; size_t out_cs;             // O_l (the caller's output at level 0)
+  Geom g;
+  Coefs cf;
+};
+
+// Wave -> (strip, segment, channel); false when the wave has no work.
+__device__ inline bool wave_coords(const Geom &g, int &lane, int &strip, int &seg, int &c) {
+  lane = threadIdx.x & 63;
+  // the wave index is uniform; readfirstlane lets the compiler keep every row
+  // index, offset and loop bound derived from it in scalar registers
+  const int wv = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  strip = wv % g.nstrips;
+  const int rest = wv / g.nstrips;
+  seg = rest % g.nsegs;
+  c = rest / g.nsegs;
+  return c < g.C;
+}
+
+// A wave touches columns outside [0, Wf) only in the first strip and in the
+// strips whose lane 63 (coarse column 62 s + 62) reaches fine column Wf - 1.
+__device__ inline bool border_strip(int strip, int Wf) {
+  return strip == 0 || 2 * (62 * strip + 62) + 1 >= Wf;
+}
+
+// --------------------------------------------------------------------------
+// down(l)
+// --------------------------------------------------------------------------
+template <int ST, int KM, bool EX, bool L0, bool MAP>
+struct DownWave {
+  using PS = PairStore<ST>;
+  using PT = typename PS::T;
+  struct RowIn {  // one fine row as loaded (raw), for the one-row-ahead prefetch
+    float g0, g1, m0, m1;
+    PT p0[KM], p1[KM];
+  };
+  const DownArgs<PT> &a;
+  int c, K, j, i0, i1, x0;
+  bool writer, border, vec_g;
+  uint32_t vx, vf0, vf1, vpx, vpf0, vpf1, vcj, vpcj;  // lane byte offsets
+  const float *gf;
+  const PT *csf;
+  float PG0, PG1, PM0, PM1;
+  float PC0[KM], PC1[KM], PS0[KM], PS1[KM];
+
+  __device__ DownWave(const DownArgs<PT> &args, int lane, int c_, int strip, int seg) : a(args) {
+    c = c_;
+    K = EX ? KM : a.cf.K;
+    j = strip * 62 + lane - 1;
+    i0 = seg * a.g.S;
+    i1 = min(i0 + a.g.S, a.g.Hc);
+    writer = lane >= 1 && lane <= 62 && j < a.g.Wc;
+    border = border_strip(strip, a.g.Wf);  // uniform
+    x0 = 2 * j;
+    const int f0 = reflect(x0, a.g.Wf), f1 = reflect(x0 + 1, a.g.Wf);
+    vx = (uint32_t)max(x0, 0) * 4u;
+    vf0 = (uint32_t)f0 * 4u;
+    vf1 = (uint32_t)f1 * 4u;
+    vpx = (uint32_t)max(x0, 0) * PS::bytes;
+    vpf0 = (uint32_t)f0 * PS::bytes;
+    vpf1 = (uint32_t)f1 * PS::bytes;
+    vcj = (uint32_t)max(j, 0) * 4u;
+    vpcj = (uint32_t)max(j, 0) * PS::bytes;
+    gf = a.gf + (size_t)c * a.gf_cs;
+    csf = L0 ? nullptr : a.csf + (size_t)c * a.csf_cs;
+    // the caller's planes (level 0) have arbitrary pitch and alignment
+    vec_g = !L0 || (((a.g.pf & 1) == 0) && ((reinterpret_cast<uintptr_t>(gf) & 7) == 0) &&
+                    (!MAP || (reinterpret_cast<uintptr_t>(a.mf) & 7) == 0));
+  }
+
+  __device__ inline void ld_f2(const Plane &p, uint32_t soff, float &x, float &y) const {
+    if (border || !vec_g) {
+      x = p.ld1(border ? vf0 : vx, soff);
+      y = p.ld1(border ? vf1 : vx + 4u, soff);
+    } else {
+      const float2 v = p.ld2(vx, soff);
+      x = v.x;
+      y = v.y;
+    }
+  }
+
+  __device__ inline void load(RowIn &d, int r) const {
+    const uint32_t fr = (uint32_t)reflect(r, a.g.Hf);
+    ld_f2(Plane(gf), fr * (uint32_t)a.g.pf * 4u, d.g0, d.g1);
+    if (MAP) ld_f2(Plane(a.mf), fr * (uint32_t)a.g.pf * 4u, d.m0, d.m1);
+    if (!L0) {
+      const uint32_t so = fr * (uint32_t)a.g.pf * PS::bytes;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {
+          const Plane p(csf + (size_t)k * a.csf_ks);
+          if (border) {
+            d.p0[k] = PS::ld(p, vpf0, so);
+            d.p1[k] = PS::ld(p, vpf1, so);
+          } else {
+            PS::ld_two(p, vpx, so, d.p0[k], d.p1[k]);
+          }
+        }
+      }
+    }
+  }
+
+  // Consume fine row r (stream role ROLE); ROLE 4 emits coarse row ci.
+  template <int ROLE>
+  __device__ inline void process(const RowIn &d, int r, int ci) {
+    float og = 0.f, om = 0.f;
+    float oc[KM], os[KM];
+    vstep<ROLE>(hred(d.g0, d.g1), PG0, PG1, og);
+    if (MAP) vstep<ROLE>(hred(d.m0, d.m1), PM0, PM1, om);
+    float s, cc;
+    sincos2pi(d.g0 * a.cf.inv_T, s, cc);
+    Harmonics h0;
+    h0.init(cc, s);
+    sincos2pi(d.g1 * a.cf.inv_T, s, cc);
+    Harmonics h1;
+    h1.init(cc, s);
+    if (L0) {
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {
+          vstep<ROLE>(hred(h0.c, h1.c), PC0[k], PC1[k], oc[k]);
+          vstep<ROLE>(hred(h0.s, h1.s), PS0[k], PS1[k], os[k]);
+          h0.next();
+          h1.next();
+        }
+      }
+    } else {
+      float acc0 = 0.f, acc1 = 0.f;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {
+          const float2 q0 = PS::cvt(d.p0[k]), q1 = PS::cvt(d.p1[k]);
+          vstep<ROLE>(hred(q0.x, q1.x), PC0[k], PC1[k], oc[k]);
+          vstep<ROLE>(hred(q0.y, q1.y), PS0[k], PS1[k], os[k]);
+          // level-l half of Eq. (14) (pairs carry at_k)
+          acc0 = fmaf(h0.s, q0.x, fmaf(-h0.c, q0.y, acc0));
+          acc1 = fmaf(h1.s, q1.x, fmaf(-h1.c, q1.y, acc1));
+          h0.next();
+          h1.next();
+        }
+      }
+      // this lane owns fine columns x0, x0+1 of rows [2 i0, 2 i1)
+      if (writer && r >= 2 * i0 && r < 2 * i1 && r < a.g.Hf) {
+        const float m0 = MAP ? d.m0 : a.cf.m, m1 = MAP ? d.m1 : a.cf.m;
+        const Plane ap(a.af + (size_t)c * a.af_cs);
+        const uint32_t so = (uint32_t)r * (uint32_t)a.g.pf * 4u;
+        const float A0 = fmaf(-m0, acc0, d.g0), A1 = fmaf(-m1, acc1, d.g1);
+        if (x0 + 1 < a.g.Wf) {
+          ap.st2(make_float2(A0, A1), vx, so);
+        } else {
+          ap.st1(A0, vx, so);
+        }
+      }
+    }
+    if (ROLE == 4 && writer && ci >= i0) {
+      const uint32_t so = (uint32_t)ci * (uint32_t)a.g.pc;
+      Plane(a.gc + (size_t)c * a.gc_cs).st1(og, vcj, so * 4u);
+      if (MAP && a.mc && c == 0) Plane(a.mc).st1(om, vcj, so * 4u);
+      const PT *cbase = a.csc + (size_t)c * a.csc_cs;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {
+          // level 1 is where the pyramids take their at_k factor
+          const float w = L0 ? a.cf.at[k] : 1.f;
+          PS::st(Plane(cbase + (size_t)k * a.csc_ks), w * oc[k], w * os[k], vpcj, so * PS::bytes);
+        }
+      }
+    }
+  }
+
+  // Row 2 i0 - 2 only seeds P1 (the running sum of coarse row i0); the loop
+  // then starts one coarse row early, and its first emission (coarse row
+  // i0 - 1, incomplete) is not stored.  A single steady-state loop body keeps
+  // the register peak that of one row plus the prefetched next row.
+  __device__ inline void run() {
+    RowIn A, B;
+    load(A, 2 * i0 - 2);
+    load(B, 2 * i0 - 1);
+    process<0>(A, 2 * i0 - 2, i0 - 1);
+    for (int i = i0 - 1; i < i1; ++i) {
+      load(A, 2 * i + 2);
+      process<3>(B, 2 * i + 1, i);
+      load(B, 2 * i + 3);
+      process<4>(A, 2 * i + 2, i);
+    }
+  }
+};
+
+template <int ST, int KM, bool EX, bool L0, bool MAP>
+__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownArgs<typename PairStore<ST>::T> a) {
+  int lane, strip, seg, c;
+  if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
+  DownWave<ST, KM, EX, L0, MAP> w(a, lane, c, strip, seg);
+  w.run();
+}
+
+// --------------------------------------------------------------------------
+// up(l)
+// --------------------------------------------------------------------------
+// Unnormalised EXPAND of one plane onto the lane's 2x2 fine block from coarse
+// rows i-1, i, i+1 at the lane's column (xm, x0, xp) and the neighbour lanes'.
+// e[0..3] = (2i, 2j), (2i, 2j+1), (2i+1, 2j), (2i+1, 2j+1).
+__device__ inline void expand4(float xm, float x0, float xp, float *e) {
+  const float ve = fmaf(6.f, x0, xm + xp);
+  const float vo = x0 + xp;
+  const float re = from_right(ve), ro = from_right(vo);
+  e[0] = fmaf(6.f, ve, from_left(ve) + re);
+  e[1] = ve + re;
+  e[2] = fmaf(6.f, vo, from_left(vo) + ro);
+  e[3] = vo + ro;
+}
+
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
+struct UpWave {
+  using PS = PairStore<ST>;
+  using PT = typename PS::T;
+  struct CRow {  // coarse row as loaded (raw): O_{l+1}, G_{l+1}, pairs, at column cj
+    float o, g;
+    PT q[KM];
+  };
+  struct FBlk {  // fine 2x2 block as loaded: G (or I), A (or I), boost
+    float g[4], b[4], m[4];
+  };
+  const UpArgs<PT> &a;
+  int c, K, j, i0, i1, x0;
+  bool writer, two, border, vec_f;
+  uint32_t vcj, vpcj, vx, vxa, vxb;  // lane byte offsets
+  const float *gc, *oc, *base, *gfp;
+  const PT *csc;
+  float *outp;
+
+  __device__ UpWave(const UpArgs<PT> &args, int lane, int c_, int strip, int seg) : a(args) {
+    const Geom &g = a.g;
+    c = c_;
+    K = EX ? KM : a.cf.K;
+    j = strip * 62 + lane - 1;
+    const int cj = cfold(j, g.Wc, g.Wf);
+    vcj = (uint32_t)cj * 4u;
+    vpcj = (uint32_t)cj * PS::bytes;
+    i0 = seg * g.S;
+    i1 = min(i0 + g.S, g.Hc);
+    writer = lane >= 1 && lane <= 62 && j < g.Wc;
+    border = border_strip(strip, g.Wf);  // uniform
+    x0 = 2 * j;
+    two = x0 + 1 < g.Wf;
+    // border waves read clamped columns (values of non-writer lanes are unused)
+    vx = (uint32_t)max(x0, 0) * 4u;
+    vxa = (uint32_t)min(max(x0, 0), g.Wf - 1) * 4u;
+    vxb = (uint32_t)min(max(x0 + 1, 0), g.Wf - 1) * 4u;
+    gfp = a.gf + (size_t)c * a.gf_cs;
+    vec_f = !L0 || (((g.pf & 1) == 0) && ((reinterpret_cast<uintptr_t>(gfp) & 7) == 0) &&
+                    (!MAP || (reinterpret_cast<uintptr_t>(a.mf) & 7) == 0) &&
+                    ((reinterpret_cast<uintptr_t>(a.out + (size_t)c * a.out_cs) & 7) == 0));
+    gc = a.gc + (size_t)c * a.gc_cs;
+    oc = HASD ? a.oc + (size_t)c * a.oc_cs : nullptr;
+    csc = a.csc + (size_t)c * a.csc_cs;
+    base = a.base + (size_t)c * a.base_cs;
+    outp = a.out + (size_t)c * a.out_cs;
+  }
+
+  __device__ inline void load_c(CRow &d, int i) const {
+    const uint32_t ci = (uint32_t)cfold(i, a.g.Hc, a.g.Hf) * (uint32_t)a.g.pc;
+    if (HASD) {
+      d.o = Plane(oc).ld1(vcj, ci * 4u);
+      d.g = Plane(gc).ld1(vcj, ci * 4u);
+    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (EX || k < K) d.q[k] = PS::ld(Plane(csc + (size_t)k * a.csc_ks), vpcj, ci * PS::bytes);
+  }
+
+  __device__ inline void ld_f2(const Plane &p, uint32_t so, float &x, float &y) const {
+    if (border) {
+      x = p.ld1(vxa, so);
+      y = p.ld1(vxb, so);
+    } else if (vec_f) {
+      const float2 v = p.ld2(vx, so);
+      x = v.x;
+      y = v.y;
+    } else {
+      x = p.ld1(vx, so);
+      y = p.ld1(vx + 4u, so);
+    }
+  }
+
+  __device__ inline void load_f(FBlk &d, int i) const {
+    const uint32_t r0 = 2 * i, r1 = min(2 * i + 1, a.g.Hf - 1);
+    const uint32_t rr[2] = {r0, r1};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t so = rr[q] * (uint32_t)a.g.pf * 4u;
+      ld_f2(Plane(gfp), so, d.g[2 * q], d.g[2 * q + 1]);
+      if (!L0) ld_f2(Plane(base), so, d.b[2 * q], d.b[2 * q + 1]);
+      if (MAP) ld_f2(Plane(a.mf), so, d.m[2 * q], d.m[2 * q + 1]);
+    }
+  }
+
+  __device__ inline void run() {
+    const Geom &g = a.g;
+    // coarse rows i-1 and i as float32, row i+1 raw (prefetched one step ahead)
+    float Dm = 0.f, D0 = 0.f, Cm[KM], C0[KM], Sm[KM], S0[KM];
+    CRow rp, rn;
+    FBlk fa, fb;
+    {
+      CRow t;
+      load_c(t, i0 - 1);
+      if (HASD) Dm = t.o - t.g;
+#pragma unroll
+      for (int k = 0; k < KM; ++k)
+        if (EX || k < K) { const float2 v = PS::cvt(t.q[k]); Cm[k] = v.x; Sm[k] = v.y; }
+      load_c(t, i0);
+      if (HASD) D0 = t.o - t.g;
+#pragma unroll
+      for (int k = 0; k < KM; ++k)
+        if (EX || k < K) { const float2 v = PS::cvt(t.q[k]); C0[k] = v.x; S0[k] = v.y; }
+    }
+    load_c(rp, i0 + 1);
+    load_f(fa, i0);
+    const Plane op(outp);
+    for (int i = i0; i < i1; ++i) {
+      load_c(rn, i + 2);
+      load_f(fb, i + 1 < i1 ? i + 1 : i);
+      const float Dp = HASD ? rp.o - rp.g : 0.f;
+      float ED[4] = {0.f, 0.f, 0.f, 0.f};
+      if (HASD) expand4(Dm, D0, Dp, ED);
+      Harmonics hm[4];
+      float acc[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        float s, cc;
+        sincos2pi(fa.g[p] * a.cf.inv_T, s, cc);
+        hm[p].init(cc, s);
+        acc[p] = 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {
+          const float2 v = PS::cvt(rp.q[k]);
+          float EC[4], ES[4];
+          expand4(Cm[k], C0[k], v.x, EC);
+          expand4(Sm[k], S0[k], v.y, ES);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            acc[p] = fmaf(hm[p].s, EC[p], fmaf(-hm[p].c, ES[p], acc[p]));
+            hm[p].next();
+          }
+          Cm[k] = C0[k];
+          C0[k] = v.x;
+          Sm[k] = S0[k];
+          S0[k] = v.y;
+        }
+      }
+      if (writer) {
+        // EXPAND weights (1 6 1)/8 and (1 1)/2 per axis, by the block position
+        const float scl[4] = {1.f / 64.f, 1.f / 16.f, 1.f / 16.f, 1.f / 4.f};
+        float o[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const float mp = MAP ? fa.m[p] : a.cf.m;
+          const float bp = L0 ? fa.g[p] : fa.b[p];
+          o[p] = fmaf(scl[p], fmaf(mp, acc[p], ED[p]), bp);
+        }
+        const uint32_t r0 = 2 * i;
+        const bool row1 = (int)r0 + 1 < g.Hf;
+        const uint32_t s0 = r0 * (uint32_t)g.pf * 4u, s1 = s0 + (uint32_t)g.pf * 4u;
+        if (two && vec_f) {
+          op.st2(make_float2(o[0], o[1]), vx, s0);
+          if (row1) op.st2(make_float2(o[2], o[3]), vx, s1);
+        } else {
+          op.st1(o[0], vx, s0);
+          if (two) op.st1(o[1], vx + 4u, s0);
+          if (row1) {
+            op.st1(o[2], vx, s1);
+            if (two) op.st1(o[3], vx + 4u, s1);
+          }
+        }
+      }
+      Dm = D0;
+      D0 = Dp;
+      rp = rn;
+      fa = fb;
+    }
+  }
+};
+
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
+__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs<typename PairStore<ST>::T> a) {
+  int lane, strip, seg, c;
+  if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
+  UpWave<ST, KM, EX, L0, MAP, HASD> w(a, lane, c, strip, seg);
+  w.run();
+}
+
+// --------------------------------------------------------------------------
+// Host-side launch sequence of one job.
+// --------------------------------------------------------------------------
+inline Geom make_geom(const Level &f, const Level &cl, int C, int S) {
+  Geom g;
+  g.Wf = f.w;
+  g.Hf = f.h;
+  g.Wc = cl.w;
+  g.Hc = cl.h;
+  g.pf = f.pitch;
+  g.pc = cl.pitch;
+  g.nstrips = (cl.w + 61) / 62;
+  g.S = S;
+  g.nsegs = (cl.h + S - 1) / S;
+  g.C = C;
+  return g;
+}
+
+// Coarse rows per wave: long segments amortise the halo rows, short ones give
+// the 256 CUs enough waves.
+inline int pick_segment(const Level &cl, int C) {
+  const long strips = (cl.w + 61) / 62;
+  int S = 64;
+  while (S > 4 && strips * ((cl.h + S - 1) / S) * C < 3072) S /= 2;
+  return S;
+}
+
+inline dim3 grid_for(const Geom &g) {
+  const long waves = (long)g.nstrips * g.nsegs * g.C;
+  return dim3((unsigned)((waves + 3) / 4), 1, 1);
+}
+
+template <int ST, int KM, bool EX, bool MAP>
+hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *hook) {
+  using T = typename PairStore<ST>::T;
+  const int L = P.levels;
+  const double pb = 2.0 * (ST == FLLF_STORE_F32 ? 4 : 2) * P.K;  // bytes of the K pairs per pixel
+  const double C = P.C;
+  auto pre = [&]() { if (hook) hook->before(st); };
+  auto post = [&](const char *name, double bytes) { if (hook) hook->after(st, name, bytes); };
+  auto G = [&](int l) { return (float *)(ws + P.lv[l].off_g); };
+  auto CS = [&](int l) { return (T *)(ws + P.lv[l].off_cs); };
+  auto O = [&](int l) { return (float *)(ws + P.lv[l].off_o); };
+  auto M = [&](int l) -> float * {
+    if (!MAP) return nullptr;
+    if (l == 0) return const_cast<float *>(P.m_map);
+    return l < L - 1 ? (float *)(ws + P.lv[l].off_m) : nullptr;
+  };
+  const Level *lv = P.lv;
+  const dim3 blk(256, 1, 1);
+  const double mapb = MAP ? 4.0 : 0.0;
+
+  // Algorithmic bytes: every plane element a launch must read or write, once.
+  for (int l = 0; l + 1 < L; ++l) {
+    DownArgs<T> a{};
+    a.gf = l == 0 ? P.in : G(l);
+    a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+    a.csf = l == 0 ? nullptr : CS(l);
+    a.csf_ks = lv[l].cs_kstride;
+    a.csf_cs = lv[l].cs_cstride;
+    a.mf = M(l);
+    a.gc = G(l + 1);
+    a.gc_cs = lv[l + 1].g_cstride;
+    a.csc = CS(l + 1);
+    a.csc_ks = lv[l + 1].cs_kstride;
+    a.csc_cs = lv[l + 1].cs_cstride;
+    a.mc = M(l + 1);
+    a.af = l == 0 ? nullptr : O(l);
+    a.af_cs = lv[l].g_cstride;
+    a.g = make_geom(lv[l], lv[l + 1], P.C, pick_segment(lv[l + 1], P.C));
+    a.cf = P.coefs;
+    pre();
+    if (l == 0) {
+      down_kernel<ST, KM, EX, true, MAP><<<grid_for(a.g), blk, 0, st>>>(a);
+      post(kDownNames[l], C * (4.0 * lv[0].n + (4.0 + pb) * lv[1].n) + mapb * (lv[0].n + lv[1].n));
+    } else {
+      down_kernel<ST, KM, EX, false, MAP><<<grid_for(a.g), blk, 0, st>>>(a);
+      post(kDownNames[l], C * ((4.0 + pb + 4.0) * lv[l].n + (4.0 + pb) * lv[l + 1].n) +
+                              mapb * (lv[l].n + lv[l + 1].n));
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    UpArgs<T> a{};
+    a.base = l == 0 ? P.in : O(l);
+    a.base_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+    a.gf = l == 0 ? P.in : G(l);
+    a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+    a.mf = M(l);
+    a.gc = G(l + 1);
+    a.gc_cs = lv[l + 1].g_cstride;
+    const bool hasd = l + 1 < L - 1;
+    a.oc = hasd ? O(l + 1) : nullptr;
+    a.oc_cs = lv[l + 1].g_cstride;
+    a.csc = CS(l + 1);
+    a.csc_ks = lv[l + 1].cs_kstride;
+    a.csc_cs = lv[l + 1].cs_cstride;
+    a.out = l == 0 ? P.out : O(l);
+    a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+    a.g = make_geom(lv[l], lv[l + 1], P.C, pick_segment(lv[l + 1], P.C));
+    a.cf = P.coefs;
+    pre();
+    if (l == 0) {
+      if (hasd) up_kernel<ST, KM, EX, true, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
+      else up_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
+    } else {
+      if (hasd) up_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
+      else up_kernel<ST, KM, EX, false, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
+    }
+    const double fine = l == 0 ? 4.0 : 8.0;               // I, or A_l and G_l
+    const double coarse = 4.0 + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
+    post(kUpNames[l], C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n) + mapb * lv[l].n);
+  }
+  return hipGetLastError();
+}
+
+// K == 4, 8, 16: exact loops; other K run the next larger loop with guards.
+template <int ST>
+hipError_t launch_storage(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h) {
+  const bool map = P.m_map != nullptr;
+#define FLLF_LAUNCH(KM, EX) \
+  return map ? launch_typed<ST, KM, EX, true>(P, ws, st, h) : launch_typed<ST, KM, EX, false>(P, ws, st, h)
+  switch (P.K) {
+    case 4: FLLF_LAUNCH(4, true);
+    case 8: FLLF_LAUNCH(8, true);
+    case 16: FLLF_LAUNCH(16, true);
+    default: break;
+  }
+  if (P.K < 8) FLLF_LAUNCH(8, false);
+  if (P.K < 16) FLLF_LAUNCH(16, false);
+  FLLF_LAUNCH(32, false);
+#undef FLLF_LAUNCH
+}
+
+}  // namespace fllf
