@@ -46,6 +46,15 @@ namespace fllf {
 // them to an SGPR so no per-lane waterfall loop is generated around the access.
 __device__ inline uint32_t sgpr(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// A lane offset the optimiser may not treat as loop-invariant: offset + const
+// is then formed at each access and folded into the instruction's immediate
+// offset, so adjacent dword loads share one VGPR and merge into dwordx2/x4.
+// (Empty asm, no instruction is emitted.)
+__device__ inline uint32_t opaque(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 struct Plane {
   __amdgpu_buffer_rsrc_t r;
   __device__ explicit Plane(const void *base)
@@ -300,7 +309,7 @@ struct DownWave {
   };
   const DownArgs<PT> &a;
   int c, K, j, i0, i1, x0;
-  bool writer, border, vec_g;
+  bool writer, border;
   uint32_t vx, vf0, vf1, vpx, vpf0, vpf1, vcj, vpcj;  // lane byte offsets
   const float *gf;
   const PT *csf;
@@ -314,7 +323,7 @@ struct DownWave {
     i0 = seg * a.g.S;
     i1 = min(i0 + a.g.S, a.g.Hc);
     writer = lane >= 1 && lane <= 62 && j < a.g.Wc;
-    border = border_strip(strip, a.g.Wf);  // uniform
+    border = sgpr(border_strip(strip, a.g.Wf));  // uniform
     x0 = 2 * j;
     const int f0 = reflect(x0, a.g.Wf), f1 = reflect(x0 + 1, a.g.Wf);
     vx = (uint32_t)max(x0, 0) * 4u;
@@ -327,37 +336,39 @@ struct DownWave {
     vpcj = (uint32_t)max(j, 0) * PS::bytes;
     gf = a.gf + (size_t)c * a.gf_cs;
     csf = L0 ? nullptr : a.csf + (size_t)c * a.csf_cs;
-    // the caller's planes (level 0) have arbitrary pitch and alignment
-    vec_g = !L0 || (((a.g.pf & 1) == 0) && ((reinterpret_cast<uintptr_t>(gf) & 7) == 0) &&
-                    (!MAP || (reinterpret_cast<uintptr_t>(a.mf) & 7) == 0));
   }
 
+  // Two fine samples (columns x0, x0+1) of one float row: folded columns in
+  // border strips, one contiguous 8-byte access otherwise.
+  template <bool BORDER>
   __device__ inline void ld_f2(const Plane &p, uint32_t soff, float &x, float &y) const {
-    if (border || !vec_g) {
-      x = p.ld1(border ? vf0 : vx, soff);
-      y = p.ld1(border ? vf1 : vx + 4u, soff);
+    if (BORDER) {
+      x = p.ld1(vf0, soff);
+      y = p.ld1(vf1, soff);
     } else {
-      const float2 v = p.ld2(vx, soff);
+      const float2 v = p.ld2(opaque(vx), soff);
       x = v.x;
       y = v.y;
     }
   }
 
+  template <bool BORDER>
   __device__ inline void load(RowIn &d, int r) const {
     const uint32_t fr = (uint32_t)reflect(r, a.g.Hf);
-    ld_f2(Plane(gf), fr * (uint32_t)a.g.pf * 4u, d.g0, d.g1);
-    if (MAP) ld_f2(Plane(a.mf), fr * (uint32_t)a.g.pf * 4u, d.m0, d.m1);
+    ld_f2<BORDER>(Plane(gf), fr * (uint32_t)a.g.pf * 4u, d.g0, d.g1);
+    if (MAP) ld_f2<BORDER>(Plane(a.mf), fr * (uint32_t)a.g.pf * 4u, d.m0, d.m1);
     if (!L0) {
       const uint32_t so = fr * (uint32_t)a.g.pf * PS::bytes;
+      const uint32_t vo = opaque(vpx);
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
           const Plane p(csf + (size_t)k * a.csf_ks);
-          if (border) {
+          if (BORDER) {
             d.p0[k] = PS::ld(p, vpf0, so);
             d.p1[k] = PS::ld(p, vpf1, so);
           } else {
-            PS::ld_two(p, vpx, so, d.p0[k], d.p1[k]);
+            PS::ld_two(p, vo, so, d.p0[k], d.p1[k]);
           }
         }
       }
@@ -436,17 +447,23 @@ struct DownWave {
   // then starts one coarse row early, and its first emission (coarse row
   // i0 - 1, incomplete) is not stored.  A single steady-state loop body keeps
   // the register peak that of one row plus the prefetched next row.
-  __device__ inline void run() {
+  template <bool BORDER>
+  __device__ inline void stream() {
     RowIn A, B;
-    load(A, 2 * i0 - 2);
-    load(B, 2 * i0 - 1);
+    load<BORDER>(A, 2 * i0 - 2);
+    load<BORDER>(B, 2 * i0 - 1);
     process<0>(A, 2 * i0 - 2, i0 - 1);
     for (int i = i0 - 1; i < i1; ++i) {
-      load(A, 2 * i + 2);
+      load<BORDER>(A, 2 * i + 2);
       process<3>(B, 2 * i + 1, i);
-      load(B, 2 * i + 3);
+      load<BORDER>(B, 2 * i + 3);
       process<4>(A, 2 * i + 2, i);
     }
+  }
+
+  // one wave-uniform branch selects the row loop of border or interior strips
+  __device__ inline void run() {
+    if (border) stream<true>(); else stream<false>();
   }
 };
 
@@ -504,7 +521,7 @@ struct UpWave {
     i0 = seg * g.S;
     i1 = min(i0 + g.S, g.Hc);
     writer = lane >= 1 && lane <= 62 && j < g.Wc;
-    border = border_strip(strip, g.Wf);  // uniform
+    border = sgpr(border_strip(strip, g.Wf));  // uniform
     x0 = 2 * j;
     two = x0 + 1 < g.Wf;
     // border waves read clamped columns (values of non-writer lanes are unused)
@@ -533,33 +550,40 @@ struct UpWave {
       if (EX || k < K) d.q[k] = PS::ld(Plane(csc + (size_t)k * a.csc_ks), vpcj, ci * PS::bytes);
   }
 
+  // Two fine samples of one float row: clamped columns in border strips, one
+  // contiguous 8-byte access otherwise.
+  template <bool BORDER>
   __device__ inline void ld_f2(const Plane &p, uint32_t so, float &x, float &y) const {
-    if (border) {
+    if (BORDER) {
       x = p.ld1(vxa, so);
       y = p.ld1(vxb, so);
-    } else if (vec_f) {
-      const float2 v = p.ld2(vx, so);
+    } else {
+      const float2 v = p.ld2(opaque(vx), so);
       x = v.x;
       y = v.y;
-    } else {
-      x = p.ld1(vx, so);
-      y = p.ld1(vx + 4u, so);
     }
   }
 
+  template <bool BORDER>
   __device__ inline void load_f(FBlk &d, int i) const {
     const uint32_t r0 = 2 * i, r1 = min(2 * i + 1, a.g.Hf - 1);
     const uint32_t rr[2] = {r0, r1};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const uint32_t so = rr[q] * (uint32_t)a.g.pf * 4u;
-      ld_f2(Plane(gfp), so, d.g[2 * q], d.g[2 * q + 1]);
-      if (!L0) ld_f2(Plane(base), so, d.b[2 * q], d.b[2 * q + 1]);
-      if (MAP) ld_f2(Plane(a.mf), so, d.m[2 * q], d.m[2 * q + 1]);
+      ld_f2<BORDER>(Plane(gfp), so, d.g[2 * q], d.g[2 * q + 1]);
+      if (!L0) ld_f2<BORDER>(Plane(base), so, d.b[2 * q], d.b[2 * q + 1]);
+      if (MAP) ld_f2<BORDER>(Plane(a.mf), so, d.m[2 * q], d.m[2 * q + 1]);
     }
   }
 
+  // one wave-uniform branch selects the row loop of border or interior strips
   __device__ inline void run() {
+    if (border) stream<true>(); else stream<false>();
+  }
+
+  template <bool BORDER>
+  __device__ inline void stream() {
     const Geom &g = a.g;
     // coarse rows i-1 and i as float32, row i+1 raw (prefetched one step ahead)
     float Dm = 0.f, D0 = 0.f, Cm[KM], C0[KM], Sm[KM], S0[KM];
@@ -579,11 +603,11 @@ struct UpWave {
         if (EX || k < K) { const float2 v = PS::cvt(t.q[k]); C0[k] = v.x; S0[k] = v.y; }
     }
     load_c(rp, i0 + 1);
-    load_f(fa, i0);
+    load_f<BORDER>(fa, i0);
     const Plane op(outp);
     for (int i = i0; i < i1; ++i) {
       load_c(rn, i + 2);
-      load_f(fb, i + 1 < i1 ? i + 1 : i);
+      load_f<BORDER>(fb, i + 1 < i1 ? i + 1 : i);
       const float Dp = HASD ? rp.o - rp.g : 0.f;
       float ED[4] = {0.f, 0.f, 0.f, 0.f};
       if (HASD) expand4(Dm, D0, Dp, ED);
@@ -678,7 +702,7 @@ inline Geom make_geom(const Level &f, const Level &cl, int C, int S) {
 inline int pick_segment(const Level &cl, int C) {
   const long strips = (cl.w + 61) / 62;
   int S = 64;
-  while (S > 4 && strips * ((cl.h + S - 1) / S) * C < 3072) S /= 2;
+  while (S > 1 && strips * ((cl.h + S - 1) / S) * C < 3072) S /= 2;
   return S;
 }
 
