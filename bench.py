@@ -21,6 +21,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_uhd_rgb_k8.txt")
+
+
+def kernel_source_digest():
+    """sha256 over the native sources (kernels and launch configuration)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2206_04681_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".h", ".hip", ".cpp")):
+            h.update(fn.encode())
+            h.update(open(os.path.join(csrc, fn), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when it is absent or was taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_digest():
+        return None
+    v = kv.get(f"{kernel}_hbm_bytes_per_launch")
+    return float(v) if v else None
 
 
 def log(msg):
@@ -94,13 +123,28 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="f32,f16,bf16")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy a buffer of this many bytes 3 times (counter calibration)")
+    ap.add_argument("--digest", action="store_true", help="print the kernel source digest and exit")
     args = ap.parse_args()
+    if args.digest:
+        print(kernel_source_digest())
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+        return
     from paper_2206_04681_amd import fllf
     from paper_2206_04681_amd.synth import UHD_RGB as w
 
@@ -112,7 +156,8 @@ def main():
     for storage in args.forms.split(","):
         forms[storage] = run_form(torch, fllf, storage, x, w, args.steps, args.warmup)
 
-    main_form = forms["f32"]
+    main_key = args.forms.split(",")[0]  # f32 unless a run selects other forms
+    main_form = forms[main_key]
     ms = main_form["ms"]
     mpix = w.height * w.width / 1e6
     dom = main_form["kernels"][0]
@@ -134,10 +179,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "fourier_llf_3840x2160_rgb", "width": w.width, "height": w.height,
                    "channels": w.channels, "levels": w.levels, "K": w.K, "sigma_r": w.sigma_r,
-                   "m": w.m, "pyramid_storage": "f32"},
+                   "m": w.m, "pyramid_storage": main_key},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(dom_avg_s * 1e6, 2),
+                     "traffic": measured_traffic(dom["name"]), "avg_launch_us": round(dom_avg_s * 1e6, 2),
                      "alg_bytes_per_launch": int(dom_bytes)},
         "step_alg_gbs": round(main_form["alg_bytes_per_step"] / (ms * 1e-3) / 1e9, 1),
         "kernels": {k: [dict(name=r["name"], launches=r["launches"] // args.steps,
@@ -145,7 +190,7 @@ def main():
                         for r in f["kernels"]] for k, f in forms.items()},
     }
     for k, f in forms.items():
-        if k != "f32":
+        if k != main_key:
             result[f"{k}_store"] = {"value": round(mpix / (f["ms"] * 1e-3), 2), "unit": "MPix/s",
                                     "ms_per_step": round(f["ms"], 5),
                                     "speedup_vs_f32": round(ms / f["ms"], 3)}
