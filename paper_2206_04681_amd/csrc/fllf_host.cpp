@@ -154,11 +154,12 @@ void fourier_terms(double s, int K, double T, double *omega, double *alpha_tilde
   }
 }
 
-// Workspace layout of one job, all planes 256-byte aligned:
-//   for l = 1..top : G_l      [C][h_l][w_l] float32
-//                    CS_l     [C][K][h_l][w_l] pairs (C~_{l,k}, S~_{l,k}) of the storage type
-//   for l = 1..top-1: O_l     [C][h_l][w_l] float32   (collapse of levels >= l)
-//                     M_l     [h_l][w_l] float32      (only with a per-pixel boost map)
+// Workspace layout of one job, all planes 256-byte aligned, rows padded to 64 pixels:
+//   for l = 1..top : G_l      [C][h_l][pitch_l] float32
+//                    CS_l     [C][h_l][pitch_l][K] pairs (C~_{l,k}, S~_{l,k}) of the storage
+//                             type, times alpha~_k: the K pairs of a pixel are one record
+//   for l = 1..top-1: O_l     [C][h_l][pitch_l] float32   (collapse of levels >= l)
+//                     M_l     [h_l][pitch_l] float32      (only with a per-pixel boost map)
 void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p) {
   std::memset(p, 0, sizeof(*p));
   p->levels = job.levels;
@@ -177,15 +178,15 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
     L.pitch = l == 0 ? w : (int)align_up((size_t)w, 64);
     L.n = (size_t)w * h;
     const size_t g_plane = align_up((size_t)L.pitch * h * 4);
-    const size_t cs_plane = align_up((size_t)L.pitch * h * pair_bytes);
+    const size_t cs_plane = align_up((size_t)L.pitch * h * pair_bytes * job.K);
     L.g_cstride = g_plane / 4;
-    L.cs_kstride = cs_plane / pair_bytes;
-    L.cs_cstride = L.cs_kstride * job.K;
+    L.cs_kstride = 1;
+    L.cs_cstride = cs_plane / pair_bytes;
     if (l >= 1) {
       L.off_g = off;
       off += g_plane * job.channels;
       L.off_cs = off;
-      off += cs_plane * job.K * job.channels;
+      off += cs_plane * job.channels;
       if (l < job.levels - 1) {
         L.off_o = off;
         off += g_plane * job.channels;
@@ -272,6 +273,15 @@ static fllf_status validate(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_sto
       return fail(ctx, FLLF_EINVAL, "job %d: range_R must be finite and > 0", i);
     if (!is_finite(j.period_T) || (j.period_T != 0.0 && j.period_T <= j.range_R))
       return fail(ctx, FLLF_EINVAL, "job %d: period_T must be 0 (fit) or > range_R", i);
+    // kernels address one channel's plane with 32-bit byte offsets: the largest
+    // (the level-1 record plane) must stay below 4 GiB
+    if (j.levels >= 2) {
+      const uint64_t w1 = (uint64_t)(j.width + 1) / 2, h1 = (uint64_t)(j.height + 1) / 2;
+      const uint64_t rec_plane = fllf::align_up(w1, 64) * h1 * (uint64_t)j.K * 2u * storage_bytes(storage);
+      if (rec_plane >= ((uint64_t)1 << 32))
+        return fail(ctx, FLLF_EINVAL, "job %d: %d x %d with K=%d needs a level-1 plane of %llu bytes (limit 4 GiB)",
+                    i, j.width, j.height, j.K, (unsigned long long)rec_plane);
+    }
     const size_t bytes = (size_t)j.width * j.height * j.channels * sizeof(float);
     const char *a = (const char *)j.in, *b = (const char *)j.out;
     if (a < b + bytes && b < a + bytes)

@@ -39,7 +39,7 @@ struct Level {
   size_t off_o;      // O_l (collapse)    float32, channels x plane   (1 <= l < top)
   size_t off_m;      // G_l[m_map]        float32, one plane           (1 <= l < top)
   size_t g_cstride;  // elements between channels of G and O
-  size_t cs_kstride; // pair elements between consecutive k
+  size_t cs_kstride; // pair elements between consecutive k (1: the K pairs of a pixel are contiguous)
   size_t cs_cstride; // pair elements between channels
 };
 

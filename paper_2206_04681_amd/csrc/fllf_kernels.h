@@ -17,7 +17,8 @@
 //
 // The Fourier pyramids are stored pre-multiplied by at_k = alpha~_k (REDUCE and
 // EXPAND are linear, so every level carries the same factor); the product-sum
-// then needs no per-term multiply.
+// then needs no per-term multiply.  The K (C~, S~) pairs of a pixel form one
+// contiguous record, so a wave reads one contiguous run of records per row.
 //
 // Memory-bound multi-plane stencils; no LDS and no MFMA.  One wave64 owns a
 // strip of 62 coarse columns (lane t <-> coarse column 62 s + t - 1; lanes 0 and
@@ -41,14 +42,14 @@ namespace fllf {
 // Callers keep every offset inside the plane they address.
 // --------------------------------------------------------------------------
 // The scalar offset operand must live in an SGPR.  Every soff passed here is
-// wave-uniform by construction (row and plane offsets), but values that went
-// through VALU arithmetic (integer division) sit in VGPRs; readfirstlane moves
-// them to an SGPR so no per-lane waterfall loop is generated around the access.
+// wave-uniform by construction (row offsets), but values that went through
+// VALU arithmetic sit in VGPRs; readfirstlane moves them to an SGPR so no
+// per-lane waterfall loop is generated around the access.
 __device__ inline uint32_t sgpr(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // A lane offset the optimiser may not treat as loop-invariant: offset + const
 // is then formed at each access and folded into the instruction's immediate
-// offset, so adjacent dword loads share one VGPR and merge into dwordx2/x4.
+// offset, so adjacent dword accesses share one VGPR and merge into dwordx2/x4.
 // (Empty asm, no instruction is emitted.)
 __device__ inline uint32_t opaque(uint32_t v) {
   asm volatile("" : "+v"(v));
@@ -65,17 +66,11 @@ struct Plane {
   __device__ inline uint32_t ldu(uint32_t voff, uint32_t soff) const {
     return __builtin_amdgcn_raw_buffer_load_b32(r, voff, sgpr(soff), 0);
   }
-  // 8- and 16-byte loads are written as adjacent dword loads, which the backend
-  // merges into one buffer_load_dwordx2 / dwordx4.  (On this toolchain the
-  // 64- and 128-bit buffer-load builtins return only dword 0 correctly.)
+  // 8-byte loads are written as two adjacent dword loads, which the backend
+  // merges into one buffer_load_dwordx2.  (On this toolchain the 64- and
+  // 128-bit buffer-load builtins return only dword 0 correctly.)
   __device__ inline float2 ld2(uint32_t voff, uint32_t soff) const {
     return make_float2(ld1(voff, soff), ld1(voff + 4u, soff));
-  }
-  __device__ inline uint2 ldu2(uint32_t voff, uint32_t soff) const {
-    return make_uint2(ldu(voff, soff), ldu(voff + 4u, soff));
-  }
-  __device__ inline float4 ld4(uint32_t voff, uint32_t soff) const {
-    return make_float4(ld1(voff, soff), ld1(voff + 4u, soff), ld1(voff + 8u, soff), ld1(voff + 12u, soff));
   }
   __device__ inline void st1(float x, uint32_t voff, uint32_t soff) const {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, voff, sgpr(soff), 0);
@@ -91,70 +86,100 @@ struct Plane {
 };
 
 // --------------------------------------------------------------------------
-// Storage of the (C, S) pairs.  Arithmetic is always float32.  Loads return
-// the raw stored value (T) so that a prefetch does not wait for the data;
-// cvt() converts at the point of use.
+// Storage of the (C, S) pairs, as DW dwords each.  Arithmetic is always
+// float32; records are loaded as raw dwords (a prefetch does not wait for the
+// data) and converted at the point of use.
 // --------------------------------------------------------------------------
 template <int S> struct PairStore;
 
 template <> struct PairStore<FLLF_STORE_F32> {
-  using T = float2;
-  static constexpr uint32_t bytes = 8;
-  __device__ static inline float2 cvt(T v) { return v; }
-  __device__ static inline T ld(const Plane &p, uint32_t voff, uint32_t soff) { return p.ld2(voff, soff); }
-  // the pairs of two adjacent pixels (voff 16-byte aligned)
-  __device__ static inline void ld_two(const Plane &p, uint32_t voff, uint32_t soff, T &a, T &b) {
-    const float4 v = p.ld4(voff, soff);
-    a = make_float2(v.x, v.y);
-    b = make_float2(v.z, v.w);
+  static constexpr int DW = 2;
+  __device__ static inline float2 cvt(const uint32_t *d) {
+    return make_float2(__builtin_bit_cast(float, d[0]), __builtin_bit_cast(float, d[1]));
   }
-  __device__ static inline void st(const Plane &p, float c, float s, uint32_t voff, uint32_t soff) {
-    p.st2(make_float2(c, s), voff, soff);
+  __device__ static inline void pack(float c, float s, uint32_t *d) {
+    d[0] = __builtin_bit_cast(uint32_t, c);
+    d[1] = __builtin_bit_cast(uint32_t, s);
   }
 };
 
 template <> struct PairStore<FLLF_STORE_F16> {
-  using T = uint32_t;
-  static constexpr uint32_t bytes = 4;
-  __device__ static inline float2 cvt(T u) {
-    const _Float16 lo = __builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
-    const _Float16 hi = __builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+  static constexpr int DW = 1;
+  __device__ static inline float2 cvt(const uint32_t *d) {
+    const _Float16 lo = __builtin_bit_cast(_Float16, (uint16_t)(d[0] & 0xffffu));
+    const _Float16 hi = __builtin_bit_cast(_Float16, (uint16_t)(d[0] >> 16));
     return make_float2((float)lo, (float)hi);
   }
-  __device__ static inline T ld(const Plane &p, uint32_t voff, uint32_t soff) { return p.ldu(voff, soff); }
-  __device__ static inline void ld_two(const Plane &p, uint32_t voff, uint32_t soff, T &a, T &b) {
-    const uint2 v = p.ldu2(voff, soff);
-    a = v.x;
-    b = v.y;
-  }
-  __device__ static inline void st(const Plane &p, float c, float s, uint32_t voff, uint32_t soff) {
+  __device__ static inline void pack(float c, float s, uint32_t *d) {
     const uint16_t lo = __builtin_bit_cast(uint16_t, (_Float16)c);
     const uint16_t hi = __builtin_bit_cast(uint16_t, (_Float16)s);
-    p.stu((uint32_t)lo | ((uint32_t)hi << 16), voff, soff);
+    d[0] = (uint32_t)lo | ((uint32_t)hi << 16);
   }
 };
 
 template <> struct PairStore<FLLF_STORE_BF16> {
-  using T = uint32_t;
-  static constexpr uint32_t bytes = 4;
+  static constexpr int DW = 1;
   __device__ static inline uint32_t to_bf16(float f) {  // round to nearest even; finite inputs
     uint32_t u = __float_as_uint(f);
     u += 0x7fffu + ((u >> 16) & 1u);
     return u >> 16;
   }
-  __device__ static inline float2 cvt(T u) {
-    return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+  __device__ static inline float2 cvt(const uint32_t *d) {
+    return make_float2(__uint_as_float(d[0] << 16), __uint_as_float(d[0] & 0xffff0000u));
   }
-  __device__ static inline T ld(const Plane &p, uint32_t voff, uint32_t soff) { return p.ldu(voff, soff); }
-  __device__ static inline void ld_two(const Plane &p, uint32_t voff, uint32_t soff, T &a, T &b) {
-    const uint2 v = p.ldu2(voff, soff);
-    a = v.x;
-    b = v.y;
-  }
-  __device__ static inline void st(const Plane &p, float c, float s, uint32_t voff, uint32_t soff) {
-    p.stu(to_bf16(c) | (to_bf16(s) << 16), voff, soff);
-  }
+  __device__ static inline void pack(float c, float s, uint32_t *d) { d[0] = to_bf16(c) | (to_bf16(s) << 16); }
 };
+
+// One pixel record: the first n dwords (n = K * DW) at voff; adjacent dword
+// accesses are merged by the backend into dwordx4 (voff must be opaque()).
+template <int NMAX, bool EX>
+__device__ inline void ld_record(const Plane &p, uint32_t voff, uint32_t soff, int n, uint32_t *d) {
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (EX || i < n) d[i] = p.ldu(voff + 4u * i, soff);
+}
+template <int NMAX, bool EX>
+__device__ inline void st_record(const Plane &p, uint32_t voff, uint32_t soff, int n, const uint32_t *d) {
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (EX || i < n) p.stu(d[i], voff + 4u * i, soff);
+}
+
+// Stores the records of the wave's writer lanes (lanes 1 .. nw, NR dwords each,
+// NR a multiple of 4) to one contiguous run starting at byte voff0 + soff.  The
+// records go through the wave's LDS slice (lane L's record at L * (NR + 4)
+// dwords; the pad spreads the lanes over the LDS banks) so that every store
+// instruction writes 64 consecutive 16-byte pieces (whole cache lines) instead
+// of one piece per record.  Only this wave touches its slice and LDS operations
+// of one wave are performed in order; the wavefront-scope fences keep the
+// compiler from reordering the slice accesses.
+template <int NR>
+constexpr int staged_slice_dwords() { return 64 * (NR + 4); }
+
+template <int NR>
+__device__ inline void st_records_staged(char *row, int lane, int nw, const uint32_t *d, uint32_t *slice) {
+  static_assert(NR % 4 == 0, "records must be whole 16-byte pieces");
+  constexpr int PIECES = NR / 4, STRIDE = NR + 4, ITER = (62 * PIECES + 63) / 64;
+#pragma unroll
+  for (int i = 0; i < PIECES; ++i)
+    *reinterpret_cast<uint4 *>(slice + lane * STRIDE + 4 * i) =
+        make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int total = nw * PIECES;  // 16-byte pieces to store, record of lane 1 first
+  uint4 v[ITER];
+#pragma unroll
+  for (int q = 0; q < ITER; ++q) {
+    const int t = min(q * 64 + lane, total - 1);
+    const int r = t / PIECES + 1, part = t - (r - 1) * PIECES;
+    v[q] = *reinterpret_cast<const uint4 *>(slice + r * STRIDE + 4 * part);
+  }
+#pragma unroll
+  for (int q = 0; q < ITER; ++q) {
+    const int t = q * 64 + lane;
+    if (t < total) *reinterpret_cast<uint4 *>(row + 16u * (uint32_t)t) = v[q];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
 
 // --------------------------------------------------------------------------
 // Index helpers
@@ -247,46 +272,45 @@ constexpr int min_waves_per_simd(int KM) { return KM <= 8 ? 2 : 1; }
 // --------------------------------------------------------------------------
 struct Geom {
   int Wf, Hf, Wc, Hc;  // fine and coarse sizes
-  int pf, pc;          // row pitches (elements) of the fine and coarse planes
+  int pf, pc;          // row pitches (pixels) of the fine and coarse planes
   int nstrips, nsegs;  // column strips (62 coarse columns each) and row segments
   int S;               // coarse rows per segment
   int C;               // channels
 };
 
-template <typename PT> struct DownArgs {
+struct DownArgs {
   const float *gf; size_t gf_cs;         // G_l (the input I at level 0)
-  const PT *csf; size_t csf_ks, csf_cs;  // level-l pairs (l >= 1)
+  const uint32_t *csf; size_t csf_cs;    // level-l pair records (l >= 1), dwords per channel
   const float *mf;                       // level-l boost plane (m_map at level 0)
   float *gc; size_t gc_cs;               // G_{l+1}
-  PT *csc; size_t csc_ks, csc_cs;        // level-(l+1) pairs
+  uint32_t *csc; size_t csc_cs;          // level-(l+1) pair records
   float *mc;                             // level-(l+1) boost plane or null
   float *af; size_t af_cs;               // A_l (l >= 1), stored in the O_l slot
   Geom g;
   Coefs cf;
 };
 
-template <typename PT> struct UpArgs {
+struct UpArgs {
   const float *base; size_t base_cs;     // A_l, or I at level 0 (may alias out)
   const float *gf; size_t gf_cs;         // G_l, or I at level 0
   const float *mf;                       // level-l boost plane, or m_map at level 0
   const float *gc; size_t gc_cs;         // G_{l+1}
   const float *oc; size_t oc_cs;         // O_{l+1} (null when l+1 is the top level)
-  const PT *csc; size_t csc_ks, csc_cs;  // level-(l+1) pairs
+  const uint32_t *csc; size_t csc_cs;    // level-(l+1) pair records
   float *out; size_t out_cs;             // O_l (the caller's output at level 0)
   Geom g;
   Coefs cf;
 };
 
-// Wave -> (strip, segment, channel); false when the wave has no work.
+// Wave -> (strip, segment, channel), all wave-uniform in scalar registers;
+// false when the wave has no work.
 __device__ inline bool wave_coords(const Geom &g, int &lane, int &strip, int &seg, int &c) {
   lane = threadIdx.x & 63;
-  // the wave index is uniform; readfirstlane lets the compiler keep every row
-  // index, offset and loop bound derived from it in scalar registers
   const int wv = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  strip = wv % g.nstrips;
+  strip = __builtin_amdgcn_readfirstlane(wv % g.nstrips);
   const int rest = wv / g.nstrips;
-  seg = rest % g.nsegs;
-  c = rest / g.nsegs;
+  seg = __builtin_amdgcn_readfirstlane(rest % g.nsegs);
+  c = __builtin_amdgcn_readfirstlane(rest / g.nsegs);
   return c < g.C;
 }
 
@@ -302,38 +326,51 @@ __device__ inline bool border_strip(int strip, int Wf) {
 template <int ST, int KM, bool EX, bool L0, bool MAP>
 struct DownWave {
   using PS = PairStore<ST>;
-  using PT = typename PS::T;
+  static constexpr int DW = PS::DW;
+  static constexpr int NR = KM * DW;  // dwords of a full record
   struct RowIn {  // one fine row as loaded (raw), for the one-row-ahead prefetch
     float g0, g1, m0, m1;
-    PT p0[KM], p1[KM];
+    uint32_t q0[NR], q1[NR];
   };
-  const DownArgs<PT> &a;
-  int c, K, j, i0, i1, x0;
+  // With exact K the coarse records are written through LDS (whole lines per store).
+  static constexpr bool STAGED = EX;
+  const DownArgs &a;
+  int c, K, nr, j, i0, i1, x0, lane, nw;
   bool writer, border;
+  uint32_t rec;                                        // bytes per pair record
   uint32_t vx, vf0, vf1, vpx, vpf0, vpf1, vcj, vpcj;  // lane byte offsets
+  uint32_t vrun;                                       // record offset of lane 1's coarse column
+  uint32_t *slice;                                     // this wave's LDS staging slice
   const float *gf;
-  const PT *csf;
+  const uint32_t *csf;
   float PG0, PG1, PM0, PM1;
   float PC0[KM], PC1[KM], PS0[KM], PS1[KM];
 
-  __device__ DownWave(const DownArgs<PT> &args, int lane, int c_, int strip, int seg) : a(args) {
+  __device__ DownWave(const DownArgs &args, int lane_, int c_, int strip, int seg, uint32_t *slice_)
+      : a(args) {
+    lane = lane_;
+    slice = slice_;
     c = c_;
     K = EX ? KM : a.cf.K;
+    nr = K * DW;
+    rec = 4u * (uint32_t)nr;
     j = strip * 62 + lane - 1;
     i0 = seg * a.g.S;
     i1 = min(i0 + a.g.S, a.g.Hc);
     writer = lane >= 1 && lane <= 62 && j < a.g.Wc;
+    nw = min(62, a.g.Wc - strip * 62);  // writer lanes are 1 .. nw
+    vrun = (uint32_t)(strip * 62) * rec;
     border = sgpr(border_strip(strip, a.g.Wf));  // uniform
     x0 = 2 * j;
     const int f0 = reflect(x0, a.g.Wf), f1 = reflect(x0 + 1, a.g.Wf);
     vx = (uint32_t)max(x0, 0) * 4u;
     vf0 = (uint32_t)f0 * 4u;
     vf1 = (uint32_t)f1 * 4u;
-    vpx = (uint32_t)max(x0, 0) * PS::bytes;
-    vpf0 = (uint32_t)f0 * PS::bytes;
-    vpf1 = (uint32_t)f1 * PS::bytes;
+    vpx = (uint32_t)max(x0, 0) * rec;
+    vpf0 = (uint32_t)f0 * rec;
+    vpf1 = (uint32_t)f1 * rec;
     vcj = (uint32_t)max(j, 0) * 4u;
-    vpcj = (uint32_t)max(j, 0) * PS::bytes;
+    vpcj = (uint32_t)max(j, 0) * rec;
     gf = a.gf + (size_t)c * a.gf_cs;
     csf = L0 ? nullptr : a.csf + (size_t)c * a.csf_cs;
   }
@@ -358,19 +395,15 @@ struct DownWave {
     ld_f2<BORDER>(Plane(gf), fr * (uint32_t)a.g.pf * 4u, d.g0, d.g1);
     if (MAP) ld_f2<BORDER>(Plane(a.mf), fr * (uint32_t)a.g.pf * 4u, d.m0, d.m1);
     if (!L0) {
-      const uint32_t so = fr * (uint32_t)a.g.pf * PS::bytes;
-      const uint32_t vo = opaque(vpx);
-#pragma unroll
-      for (int k = 0; k < KM; ++k) {
-        if (EX || k < K) {
-          const Plane p(csf + (size_t)k * a.csf_ks);
-          if (BORDER) {
-            d.p0[k] = PS::ld(p, vpf0, so);
-            d.p1[k] = PS::ld(p, vpf1, so);
-          } else {
-            PS::ld_two(p, vo, so, d.p0[k], d.p1[k]);
-          }
-        }
+      const Plane p(csf);
+      const uint32_t so = fr * (uint32_t)a.g.pf * rec;
+      if (BORDER) {
+        ld_record<NR, EX>(p, opaque(vpf0), so, nr, d.q0);
+        ld_record<NR, EX>(p, opaque(vpf1), so, nr, d.q1);
+      } else {
+        const uint32_t vo = opaque(vpx);
+        ld_record<NR, EX>(p, vo, so, nr, d.q0);
+        ld_record<NR, EX>(p, vo + rec, so, nr, d.q1);
       }
     }
   }
@@ -404,7 +437,7 @@ struct DownWave {
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
-          const float2 q0 = PS::cvt(d.p0[k]), q1 = PS::cvt(d.p1[k]);
+          const float2 q0 = PS::cvt(&d.q0[k * DW]), q1 = PS::cvt(&d.q1[k * DW]);
           vstep<ROLE>(hred(q0.x, q1.x), PC0[k], PC1[k], oc[k]);
           vstep<ROLE>(hred(q0.y, q1.y), PS0[k], PS1[k], os[k]);
           // level-l half of Eq. (14) (pairs carry at_k)
@@ -427,18 +460,27 @@ struct DownWave {
         }
       }
     }
-    if (ROLE == 4 && writer && ci >= i0) {
+    if (ROLE == 4 && ci >= i0) {  // wave-uniform
       const uint32_t so = (uint32_t)ci * (uint32_t)a.g.pc;
-      Plane(a.gc + (size_t)c * a.gc_cs).st1(og, vcj, so * 4u);
-      if (MAP && a.mc && c == 0) Plane(a.mc).st1(om, vcj, so * 4u);
-      const PT *cbase = a.csc + (size_t)c * a.csc_cs;
+      if (writer) {
+        Plane(a.gc + (size_t)c * a.gc_cs).st1(og, vcj, so * 4u);
+        if (MAP && a.mc && c == 0) Plane(a.mc).st1(om, vcj, so * 4u);
+      }
+      uint32_t q[NR];
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
           // level 1 is where the pyramids take their at_k factor
           const float w = L0 ? a.cf.at[k] : 1.f;
-          PS::st(Plane(cbase + (size_t)k * a.csc_ks), w * oc[k], w * os[k], vpcj, so * PS::bytes);
+          PS::pack(w * oc[k], w * os[k], &q[k * DW]);
         }
+      }
+      const Plane cp(a.csc + (size_t)c * a.csc_cs);
+      if (STAGED) {
+        char *row = reinterpret_cast<char *>(a.csc + (size_t)c * a.csc_cs) + (size_t)so * rec + vrun;
+        st_records_staged<NR>(row, lane, nw, q, slice);
+      } else if (writer) {
+        st_record<NR, EX>(cp, opaque(vpcj), so * rec, nr, q);
       }
     }
   }
@@ -468,10 +510,13 @@ struct DownWave {
 };
 
 template <int ST, int KM, bool EX, bool L0, bool MAP>
-__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownArgs<typename PairStore<ST>::T> a) {
+__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownArgs a) {
+  using W = DownWave<ST, KM, EX, L0, MAP>;
+  constexpr int SLICE = W::STAGED ? staged_slice_dwords<W::NR>() : 1;
+  __shared__ uint32_t stage[4 * SLICE];
   int lane, strip, seg, c;
   if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
-  DownWave<ST, KM, EX, L0, MAP> w(a, lane, c, strip, seg);
+  W w(a, lane, c, strip, seg, stage + (threadIdx.x >> 6) * SLICE);
   w.run();
 }
 
@@ -494,30 +539,33 @@ __device__ inline void expand4(float xm, float x0, float xp, float *e) {
 template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
 struct UpWave {
   using PS = PairStore<ST>;
-  using PT = typename PS::T;
-  struct CRow {  // coarse row as loaded (raw): O_{l+1}, G_{l+1}, pairs, at column cj
+  static constexpr int DW = PS::DW;
+  static constexpr int NR = KM * DW;
+  struct CRow {  // coarse row as loaded (raw): O_{l+1}, G_{l+1}, pair record, at column cj
     float o, g;
-    PT q[KM];
+    uint32_t q[NR];
   };
   struct FBlk {  // fine 2x2 block as loaded: G (or I), A (or I), boost
     float g[4], b[4], m[4];
   };
-  const UpArgs<PT> &a;
-  int c, K, j, i0, i1, x0;
+  const UpArgs &a;
+  int c, K, nr, j, i0, i1, x0;
   bool writer, two, border, vec_f;
-  uint32_t vcj, vpcj, vx, vxa, vxb;  // lane byte offsets
+  uint32_t rec, vcj, vpcj, vx, vxa, vxb;  // record bytes, lane byte offsets
   const float *gc, *oc, *base, *gfp;
-  const PT *csc;
+  const uint32_t *csc;
   float *outp;
 
-  __device__ UpWave(const UpArgs<PT> &args, int lane, int c_, int strip, int seg) : a(args) {
+  __device__ UpWave(const UpArgs &args, int lane, int c_, int strip, int seg) : a(args) {
     const Geom &g = a.g;
     c = c_;
     K = EX ? KM : a.cf.K;
+    nr = K * DW;
+    rec = 4u * (uint32_t)nr;
     j = strip * 62 + lane - 1;
     const int cj = cfold(j, g.Wc, g.Wf);
     vcj = (uint32_t)cj * 4u;
-    vpcj = (uint32_t)cj * PS::bytes;
+    vpcj = (uint32_t)cj * rec;
     i0 = seg * g.S;
     i1 = min(i0 + g.S, g.Hc);
     writer = lane >= 1 && lane <= 62 && j < g.Wc;
@@ -529,14 +577,13 @@ struct UpWave {
     vxa = (uint32_t)min(max(x0, 0), g.Wf - 1) * 4u;
     vxb = (uint32_t)min(max(x0 + 1, 0), g.Wf - 1) * 4u;
     gfp = a.gf + (size_t)c * a.gf_cs;
-    vec_f = !L0 || (((g.pf & 1) == 0) && ((reinterpret_cast<uintptr_t>(gfp) & 7) == 0) &&
-                    (!MAP || (reinterpret_cast<uintptr_t>(a.mf) & 7) == 0) &&
-                    ((reinterpret_cast<uintptr_t>(a.out + (size_t)c * a.out_cs) & 7) == 0));
+    outp = a.out + (size_t)c * a.out_cs;
+    // the caller's output (level 0) has arbitrary pitch and alignment
+    vec_f = !L0 || (((g.pf & 1) == 0) && ((reinterpret_cast<uintptr_t>(outp) & 7) == 0));
     gc = a.gc + (size_t)c * a.gc_cs;
     oc = HASD ? a.oc + (size_t)c * a.oc_cs : nullptr;
     csc = a.csc + (size_t)c * a.csc_cs;
     base = a.base + (size_t)c * a.base_cs;
-    outp = a.out + (size_t)c * a.out_cs;
   }
 
   __device__ inline void load_c(CRow &d, int i) const {
@@ -545,9 +592,7 @@ struct UpWave {
       d.o = Plane(oc).ld1(vcj, ci * 4u);
       d.g = Plane(gc).ld1(vcj, ci * 4u);
     }
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-      if (EX || k < K) d.q[k] = PS::ld(Plane(csc + (size_t)k * a.csc_ks), vpcj, ci * PS::bytes);
+    ld_record<NR, EX>(Plane(csc), opaque(vpcj), ci * rec, nr, d.q);
   }
 
   // Two fine samples of one float row: clamped columns in border strips, one
@@ -595,12 +640,12 @@ struct UpWave {
       if (HASD) Dm = t.o - t.g;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
-        if (EX || k < K) { const float2 v = PS::cvt(t.q[k]); Cm[k] = v.x; Sm[k] = v.y; }
+        if (EX || k < K) { const float2 v = PS::cvt(&t.q[k * DW]); Cm[k] = v.x; Sm[k] = v.y; }
       load_c(t, i0);
       if (HASD) D0 = t.o - t.g;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
-        if (EX || k < K) { const float2 v = PS::cvt(t.q[k]); C0[k] = v.x; S0[k] = v.y; }
+        if (EX || k < K) { const float2 v = PS::cvt(&t.q[k * DW]); C0[k] = v.x; S0[k] = v.y; }
     }
     load_c(rp, i0 + 1);
     load_f<BORDER>(fa, i0);
@@ -623,7 +668,7 @@ struct UpWave {
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
-          const float2 v = PS::cvt(rp.q[k]);
+          const float2 v = PS::cvt(&rp.q[k * DW]);
           float EC[4], ES[4];
           expand4(Cm[k], C0[k], v.x, EC);
           expand4(Sm[k], S0[k], v.y, ES);
@@ -672,7 +717,7 @@ struct UpWave {
 };
 
 template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
-__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs<typename PairStore<ST>::T> a) {
+__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs a) {
   int lane, strip, seg, c;
   if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
   UpWave<ST, KM, EX, L0, MAP, HASD> w(a, lane, c, strip, seg);
@@ -713,14 +758,14 @@ inline dim3 grid_for(const Geom &g) {
 
 template <int ST, int KM, bool EX, bool MAP>
 hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *hook) {
-  using T = typename PairStore<ST>::T;
   const int L = P.levels;
-  const double pb = 2.0 * (ST == FLLF_STORE_F32 ? 4 : 2) * P.K;  // bytes of the K pairs per pixel
+  const int dwp = PairStore<ST>::DW;                  // dwords per pair
+  const double pb = 4.0 * dwp * P.K;                  // bytes of the K pairs per pixel
   const double C = P.C;
   auto pre = [&]() { if (hook) hook->before(st); };
   auto post = [&](const char *name, double bytes) { if (hook) hook->after(st, name, bytes); };
   auto G = [&](int l) { return (float *)(ws + P.lv[l].off_g); };
-  auto CS = [&](int l) { return (T *)(ws + P.lv[l].off_cs); };
+  auto CS = [&](int l) { return (uint32_t *)(ws + P.lv[l].off_cs); };
   auto O = [&](int l) { return (float *)(ws + P.lv[l].off_o); };
   auto M = [&](int l) -> float * {
     if (!MAP) return nullptr;
@@ -733,18 +778,16 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
 
   // Algorithmic bytes: every plane element a launch must read or write, once.
   for (int l = 0; l + 1 < L; ++l) {
-    DownArgs<T> a{};
+    DownArgs a{};
     a.gf = l == 0 ? P.in : G(l);
     a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
     a.csf = l == 0 ? nullptr : CS(l);
-    a.csf_ks = lv[l].cs_kstride;
-    a.csf_cs = lv[l].cs_cstride;
+    a.csf_cs = lv[l].cs_cstride * dwp;
     a.mf = M(l);
     a.gc = G(l + 1);
     a.gc_cs = lv[l + 1].g_cstride;
     a.csc = CS(l + 1);
-    a.csc_ks = lv[l + 1].cs_kstride;
-    a.csc_cs = lv[l + 1].cs_cstride;
+    a.csc_cs = lv[l + 1].cs_cstride * dwp;
     a.mc = M(l + 1);
     a.af = l == 0 ? nullptr : O(l);
     a.af_cs = lv[l].g_cstride;
@@ -761,7 +804,7 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
     }
   }
   for (int l = L - 2; l >= 0; --l) {
-    UpArgs<T> a{};
+    UpArgs a{};
     a.base = l == 0 ? P.in : O(l);
     a.base_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
     a.gf = l == 0 ? P.in : G(l);
@@ -773,8 +816,7 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
     a.oc = hasd ? O(l + 1) : nullptr;
     a.oc_cs = lv[l + 1].g_cstride;
     a.csc = CS(l + 1);
-    a.csc_ks = lv[l + 1].cs_kstride;
-    a.csc_cs = lv[l + 1].cs_cstride;
+    a.csc_cs = lv[l + 1].cs_cstride * dwp;
     a.out = l == 0 ? P.out : O(l);
     a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
     a.g = make_geom(lv[l], lv[l + 1], P.C, pick_segment(lv[l + 1], P.C));

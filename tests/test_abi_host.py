@@ -95,7 +95,7 @@ def _expected_footprint(w, h, C, L, K, pair_bytes, has_map=False):
     for l in range(1, L):
         wl, hl = -(-w // 2 ** l), -(-h // 2 ** l)
         n = (wl + 63) // 64 * 64 * hl  # rows padded to 64 elements
-        tot += al(4 * n) * C + al(pair_bytes * n) * K * C
+        tot += al(4 * n) * C + al(pair_bytes * n * K) * C  # K pairs per pixel record
         if l < L - 1:
             tot += al(4 * n) * C + (al(4 * n) if has_map else 0)
     return tot
