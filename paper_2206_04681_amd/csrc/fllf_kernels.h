@@ -744,10 +744,26 @@ inline Geom make_geom(const Level &f, const Level &cl, int C, int S) {
 
 // Coarse rows per wave: long segments amortise the halo rows, short ones give
 // the 256 CUs enough waves.
-inline int pick_segment(const Level &cl, int C) {
+// Rows per wave segment.  Shorter segments give more waves (latency hiding,
+// fewer idle SIMDs in the last round) but re-read more halo rows.  The level-0
+// kernels read little per fine row and want many waves; the kernels that read a
+// fine level of (C, S) records want long segments.  Measured on the 4K workload.
+#ifndef FLLF_WAVES_DOWN0
+#define FLLF_WAVES_DOWN0 12288
+#endif
+#ifndef FLLF_WAVES_DOWN
+#define FLLF_WAVES_DOWN 1536
+#endif
+#ifndef FLLF_WAVES_UP0
+#define FLLF_WAVES_UP0 12288
+#endif
+#ifndef FLLF_WAVES_UP
+#define FLLF_WAVES_UP 1536
+#endif
+inline int pick_segment(const Level &cl, int C, long target) {
   const long strips = (cl.w + 61) / 62;
   int S = 64;
-  while (S > 1 && strips * ((cl.h + S - 1) / S) * C < 3072) S /= 2;
+  while (S > 1 && strips * ((cl.h + S - 1) / S) * C < target) S /= 2;
   return S;
 }
 
@@ -791,7 +807,8 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
     a.mc = M(l + 1);
     a.af = l == 0 ? nullptr : O(l);
     a.af_cs = lv[l].g_cstride;
-    a.g = make_geom(lv[l], lv[l + 1], P.C, pick_segment(lv[l + 1], P.C));
+    a.g = make_geom(lv[l], lv[l + 1], P.C,
+                    pick_segment(lv[l + 1], P.C, l == 0 ? FLLF_WAVES_DOWN0 : FLLF_WAVES_DOWN));
     a.cf = P.coefs;
     pre();
     if (l == 0) {
@@ -819,7 +836,8 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
     a.csc_cs = lv[l + 1].cs_cstride * dwp;
     a.out = l == 0 ? P.out : O(l);
     a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
-    a.g = make_geom(lv[l], lv[l + 1], P.C, pick_segment(lv[l + 1], P.C));
+    a.g = make_geom(lv[l], lv[l + 1], P.C,
+                    pick_segment(lv[l + 1], P.C, l == 0 ? FLLF_WAVES_UP0 : FLLF_WAVES_UP));
     a.cf = P.coefs;
     pre();
     if (l == 0) {
