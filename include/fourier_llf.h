@@ -92,9 +92,66 @@ fllf_status fourier_llf_workspace_size(const fllf_ctx *ctx, const fllf_job *jobs
 /* Filter n jobs (n >= 1, sizes/K/sigma_r may differ) on `hip_stream` (a
  * hipStream_t; NULL = the legacy default stream).  `workspace` is a device buffer
  * of at least the size returned by fourier_llf_workspace_size, 256-byte aligned,
- * owned by the caller and not used by anything else until the stream syncs. */
+ * owned by the caller and not used by anything else until the stream syncs.
+ *
+ * n >= 2 is the batched form: each pass of the filter (REDUCE to level l + 1,
+ * then the product-sum and collapse at level l) runs for all jobs that have it
+ * as one launch per kernel class (K loop, boost map, top level), the launches
+ * finding their jobs in a table at the start of the workspace.  The table is
+ * copied from pinned host memory held by the context, on the stream.  Each
+ * job's output equals that of a single-job run bit for bit. */
 fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
                             size_t ws_bytes, void *hip_stream);
+
+/* ---- launch shape: tuning and autotuning --------------------------------- */
+
+/* Launch-shape parameters of a context (index: meaning):
+ *   FLLF_TUNE_DOWN0, FLLF_TUNE_DOWN, FLLF_TUNE_UP0, FLLF_TUNE_UP: the number of
+ *     waves the REDUCE pass from level 0 / from levels >= 1 and the collapse
+ *     pass to level 0 / to levels >= 1 aim for when they split their rows into
+ *     segments (more waves = shorter segments = more halo rows re-read);
+ *   FLLF_TUNE_GRID_CAP: 0 = a batched launch has one wave per work item; c > 0
+ *     = at most c times the blocks resident on the device at once, each wave
+ *     looping over work items (persistent launch). */
+enum {
+  FLLF_TUNE_DOWN0 = 0,
+  FLLF_TUNE_DOWN = 1,
+  FLLF_TUNE_UP0 = 2,
+  FLLF_TUNE_UP = 3,
+  FLLF_TUNE_GRID_CAP = 4,
+  FLLF_TUNE_PARAMS = 5
+};
+
+/* Set the context's parameters; params[i] <= 0 for i < FLLF_TUNE_GRID_CAP, or
+ * params == NULL, restores the built-in value.  Results do not depend on them. */
+fllf_status fourier_llf_set_tuning(fllf_ctx *ctx, const int32_t *params);
+/* Read the context's parameters into params[0 .. FLLF_TUNE_PARAMS-1]. */
+fllf_status fourier_llf_get_tuning(const fllf_ctx *ctx, int32_t *params);
+
+/* Autotuner: times fourier_llf_run of these jobs (same arguments as run) for
+ * candidate values of each parameter in turn (coordinate descent; each
+ * candidate 1 warm-up and `reps` timed runs, reps >= 1), keeps the fastest in
+ * the context and writes them to chosen[0 .. FLLF_TUNE_PARAMS-1] (may be NULL).
+ * Synchronous: returns after the stream has drained.  The workspace contents
+ * and the jobs' outputs are overwritten. */
+fllf_status fourier_llf_autotune(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
+                                 size_t ws_bytes, void *hip_stream, int reps, int32_t *chosen);
+
+/* ---- captured schedules (HIP graphs) ------------------------------------- */
+
+typedef struct fllf_graph fllf_graph; /* opaque */
+
+/* Capture the launches fourier_llf_run would make for these jobs into an
+ * instantiated HIP graph.  The batch table is written to the workspace now
+ * (synchronously); the graph binds the jobs' in/out/m_map pointers and the
+ * workspace, which must stay valid and must not be used for anything else
+ * while the graph is in use.  Uses the context's tuning at capture time. */
+fllf_status fourier_llf_graph_create(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
+                                     size_t ws_bytes, fllf_graph **out);
+/* Enqueue one replay of the captured schedule on `hip_stream`. */
+fllf_status fourier_llf_graph_launch(fllf_graph *graph, void *hip_stream);
+/* Release the graph.  NULL-safe.  The caller must have synchronised its streams. */
+void fourier_llf_graph_destroy(fllf_graph *graph);
 
 /* Release the context.  NULL-safe.  The caller must have synchronised its streams. */
 void fourier_llf_destroy(fllf_ctx *ctx);

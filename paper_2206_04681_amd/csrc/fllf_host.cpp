@@ -71,6 +71,17 @@ struct fllf_ctx {
   fllf_storage storage;
   std::string last_error;
   EventTimer *timer = nullptr;
+  fllf::Tuning tune = fllf::default_tuning();
+  // pinned host staging of the batch table; stage_ev marks the end of its last copy
+  void *stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_ev = nullptr;
+};
+
+struct fllf_graph {
+  int device;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -218,13 +229,14 @@ const char *const kUpNames[kMaxLevels] = {"up_l0", "up_l1", "up_l2",  "up_l3",  
                                           "up_l6", "up_l7", "up_l8",  "up_l9",  "up_l10", "up_l11",
                                           "up_l12", "up_l13", "up_l14", "up_l15"};
 
-hipError_t launch_job(const JobPlan &P, fllf_storage storage, char *ws, hipStream_t st, LaunchHook *h) {
+hipError_t launch_job(const JobPlan &P, fllf_storage storage, char *ws, hipStream_t st, LaunchHook *h,
+                      const Tuning &tu) {
   if (P.levels == 1)
     return hipMemcpyAsync(P.out, P.in, P.lv[0].n * P.C * sizeof(float), hipMemcpyDeviceToDevice, st);
   switch (storage) {
-    case FLLF_STORE_F16: return launch_job_f16(P, ws, st, h);
-    case FLLF_STORE_BF16: return launch_job_bf16(P, ws, st, h);
-    default: return launch_job_f32(P, ws, st, h);
+    case FLLF_STORE_F16: return launch_job_f16(P, ws, st, h, tu);
+    case FLLF_STORE_BF16: return launch_job_bf16(P, ws, st, h, tu);
+    default: return launch_job_f32(P, ws, st, h, tu);
   }
 }
 
@@ -287,6 +299,18 @@ static fllf_status validate(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_sto
     if (a < b + bytes && b < a + bytes)
       return fail(ctx, FLLF_EINVAL, "job %d: in and out overlap", i);
   }
+  // in a batch every output must be disjoint from every other job's input and output
+  for (int i = 0; i < n && n > 1; ++i) {
+    const char *oi = (const char *)jobs[i].out;
+    const size_t bi = (size_t)jobs[i].width * jobs[i].height * jobs[i].channels * sizeof(float);
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const size_t bj = (size_t)jobs[j].width * jobs[j].height * jobs[j].channels * sizeof(float);
+      const char *ij = (const char *)jobs[j].in, *oj = (const char *)jobs[j].out;
+      if ((oi < ij + bj && ij < oi + bi) || (oi < oj + bj && oj < oi + bi))
+        return fail(ctx, FLLF_EINVAL, "job %d: output overlaps job %d's input or output", i, j);
+    }
+  }
   return FLLF_OK;
 }
 
@@ -326,6 +350,11 @@ fllf_status fourier_llf_create(fllf_ctx **out, int device, fllf_storage storage)
 
 void fourier_llf_destroy(fllf_ctx *ctx) {
   if (!ctx) return;
+  if (ctx->stage_ev) {
+    (void)hipEventSynchronize(ctx->stage_ev);
+    (void)hipEventDestroy(ctx->stage_ev);
+  }
+  if (ctx->stage) (void)hipHostFree(ctx->stage);
   delete ctx->timer;
   delete ctx;
 }
@@ -381,18 +410,32 @@ const char *fourier_llf_last_error(const fllf_ctx *ctx) {
   return g_last_error.c_str();
 }
 
+// Plans every job; the jobs' workspaces follow the batch table (n >= 2).
+static void plan_all(const fllf_job *jobs, int n, fllf_storage storage, std::vector<fllf::JobPlan> *plans,
+                     size_t *table, size_t *total) {
+  plans->resize(n);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    fllf::plan_job(jobs[i], storage, off, &(*plans)[i]);
+    off += (*plans)[i].bytes;
+  }
+  *table = fllf::batch_table_bytes(plans->data(), n, storage);
+  off = *table;
+  for (int i = 0; i < n; ++i) {
+    fllf::plan_job(jobs[i], storage, off, &(*plans)[i]);
+    off += (*plans)[i].bytes;
+  }
+  *total = off;
+}
+
 static fllf_status footprint(fllf_ctx *c, const fllf_job *jobs, int n, fllf_storage storage,
                              size_t *bytes) {
   if (!bytes) return fail(c, FLLF_EINVAL, "workspace size: bytes is NULL");
   fllf_status st = validate(c, jobs, n, storage);
   if (st != FLLF_OK) return st;
-  size_t total = 0;
-  for (int i = 0; i < n; ++i) {
-    fllf::JobPlan p;
-    fllf::plan_job(jobs[i], storage, total, &p);
-    total += p.bytes;
-  }
-  *bytes = total;
+  std::vector<fllf::JobPlan> plans;
+  size_t table = 0;
+  plan_all(jobs, n, storage, &plans, &table, bytes);
   return FLLF_OK;
 }
 
@@ -406,39 +449,212 @@ fllf_status fourier_llf_workspace_size(const fllf_ctx *ctx, const fllf_job *jobs
   return footprint(const_cast<fllf_ctx *>(ctx), jobs, n, ctx->storage, bytes);
 }
 
-fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
-                            size_t ws_bytes, void *hip_stream) {
-  if (!ctx) return fail(nullptr, FLLF_EINVAL, "run: ctx is NULL");
+// Checks shared by run, autotune and graph capture; plans the jobs.
+static fllf_status prepare(fllf_ctx *ctx, const char *who, const fllf_job *jobs, int n, void *workspace,
+                           size_t ws_bytes, std::vector<fllf::JobPlan> *plans) {
+  if (!ctx) return fail(nullptr, FLLF_EINVAL, "%s: ctx is NULL", who);
   fllf_status st = validate(ctx, jobs, n, ctx->storage);
   if (st != FLLF_OK) return st;
-  size_t need = 0;
-  fourier_llf_workspace_size(ctx, jobs, n, &need);
-  if (need > 0 && !workspace) return fail(ctx, FLLF_EINVAL, "run: workspace is NULL");
+  size_t table = 0, need = 0;
+  plan_all(jobs, n, ctx->storage, plans, &table, &need);
+  if (need > 0 && !workspace) return fail(ctx, FLLF_EINVAL, "%s: workspace is NULL", who);
   if (ws_bytes < need)
-    return fail(ctx, FLLF_ENOMEM, "run: workspace has %zu bytes, %zu needed", ws_bytes, need);
+    return fail(ctx, FLLF_ENOMEM, "%s: workspace has %zu bytes, %zu needed", who, ws_bytes, need);
   if (((uintptr_t)workspace) % fllf::kAlign != 0)
-    return fail(ctx, FLLF_EINVAL, "run: workspace must be %zu-byte aligned", fllf::kAlign);
+    return fail(ctx, FLLF_EINVAL, "%s: workspace must be %zu-byte aligned", who, fllf::kAlign);
   for (int i = 0; i < n; ++i) {
     const char *wsb = (const char *)workspace, *o = (const char *)jobs[i].out;
     size_t ob = (size_t)jobs[i].width * jobs[i].height * jobs[i].channels * sizeof(float);
     if (need > 0 && o < wsb + need && wsb < o + ob)
-      return fail(ctx, FLLF_EINVAL, "run: job %d output overlaps the workspace", i);
+      return fail(ctx, FLLF_EINVAL, "%s: job %d output overlaps the workspace", who, i);
   }
   hipError_t e = hipSetDevice(ctx->device);
-  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "run: hipSetDevice: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "%s: hipSetDevice: %s", who, hipGetErrorString(e));
   e = hipGetLastError();  // surface earlier asynchronous faults
-  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "run: pending HIP error: %s", hipGetErrorString(e));
-  hipStream_t stream = (hipStream_t)hip_stream;
-  size_t base = 0;
-  for (int i = 0; i < n; ++i) {
-    fllf::JobPlan p;
-    fllf::plan_job(jobs[i], ctx->storage, base, &p);
-    base += p.bytes;
-    e = fllf::launch_job(p, ctx->storage, (char *)workspace, stream, ctx->timer);
-    if (e != hipSuccess)
-      return fail(ctx, FLLF_EDEVICE, "run: launch of job %d failed: %s", i, hipGetErrorString(e));
-  }
+  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "%s: pending HIP error: %s", who, hipGetErrorString(e));
   return FLLF_OK;
+}
+
+// Copies a batch table into the workspace on `stream` through the context's
+// pinned staging buffer.
+static fllf_status upload_table(fllf_ctx *ctx, const fllf::BatchSchedule &s, void *ws, hipStream_t stream) {
+  if (s.table_bytes == 0) return FLLF_OK;
+  hipError_t e = hipSuccess;
+  if (ctx->stage_ev) e = hipEventSynchronize(ctx->stage_ev);  // the previous copy has read the buffer
+  if (e == hipSuccess && ctx->stage_cap < s.table_bytes) {
+    if (ctx->stage) e = hipHostFree(ctx->stage);
+    ctx->stage = nullptr;
+    ctx->stage_cap = 0;
+    const size_t cap = std::max(s.table_bytes, (size_t)1 << 20);
+    if (e == hipSuccess) e = hipHostMalloc(&ctx->stage, cap, hipHostMallocDefault);
+    if (e == hipSuccess) ctx->stage_cap = cap;
+  }
+  if (e == hipSuccess && !ctx->stage_ev) e = hipEventCreateWithFlags(&ctx->stage_ev, hipEventDisableTiming);
+  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "batch table staging: %s", hipGetErrorString(e));
+  std::memcpy(ctx->stage, s.blob.data(), s.table_bytes);
+  e = hipMemcpyAsync(ws, ctx->stage, s.table_bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventRecord(ctx->stage_ev, stream);
+  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "batch table upload: %s", hipGetErrorString(e));
+  return FLLF_OK;
+}
+
+// Enqueues planned jobs with the given tuning (no validation).
+static fllf_status enqueue(fllf_ctx *ctx, const std::vector<fllf::JobPlan> &plans, void *workspace,
+                           hipStream_t stream, const fllf::Tuning &tu, fllf::LaunchHook *hook) {
+  const int n = (int)plans.size();
+  hipError_t e = hipSuccess;
+  if (n == 1) {
+    e = fllf::launch_job(plans[0], ctx->storage, (char *)workspace, stream, hook, tu);
+    if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "run: launch failed: %s", hipGetErrorString(e));
+    return FLLF_OK;
+  }
+  fllf::BatchSchedule sched;
+  fllf::build_batch(plans.data(), n, ctx->storage, (char *)workspace, tu, &sched);
+  fllf_status st = upload_table(ctx, sched, workspace, stream);
+  if (st != FLLF_OK) return st;
+  e = fllf::launch_batch(sched, ctx->storage, (char *)workspace, stream, hook, tu);
+  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "run: batched launch failed: %s", hipGetErrorString(e));
+  return FLLF_OK;
+}
+
+fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
+                            size_t ws_bytes, void *hip_stream) {
+  std::vector<fllf::JobPlan> plans;
+  fllf_status st = prepare(ctx, "run", jobs, n, workspace, ws_bytes, &plans);
+  if (st != FLLF_OK) return st;
+  return enqueue(ctx, plans, workspace, (hipStream_t)hip_stream, ctx->tune, ctx->timer);
+}
+
+fllf_status fourier_llf_set_tuning(fllf_ctx *ctx, const int32_t *params) {
+  if (!ctx) return fail(nullptr, FLLF_EINVAL, "set_tuning: ctx is NULL");
+  const fllf::Tuning d = fllf::default_tuning();
+  fllf::Tuning t = d;
+  if (params) {
+    for (int i = 0; i < fllf::kTuneGridCap; ++i) t.p[i] = params[i] > 0 ? params[i] : d.p[i];
+    if (params[fllf::kTuneGridCap] < 0 || params[fllf::kTuneGridCap] > 1024)
+      return fail(ctx, FLLF_EINVAL, "set_tuning: grid cap %d outside [0, 1024]", params[fllf::kTuneGridCap]);
+    t.p[fllf::kTuneGridCap] = params[fllf::kTuneGridCap];
+  }
+  ctx->tune = t;
+  return FLLF_OK;
+}
+
+fllf_status fourier_llf_get_tuning(const fllf_ctx *ctx, int32_t *params) {
+  if (!ctx || !params) return fail(nullptr, FLLF_EINVAL, "get_tuning: ctx and params must be non-NULL");
+  for (int i = 0; i < fllf::kTuneParams; ++i) params[i] = ctx->tune.p[i];
+  return FLLF_OK;
+}
+
+fllf_status fourier_llf_autotune(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
+                                 size_t ws_bytes, void *hip_stream, int reps, int32_t *chosen) {
+  std::vector<fllf::JobPlan> plans;
+  fllf_status st = prepare(ctx, "autotune", jobs, n, workspace, ws_bytes, &plans);
+  if (st != FLLF_OK) return st;
+  if (reps < 1 || reps > 1000) return fail(ctx, FLLF_EINVAL, "autotune: reps=%d outside [1, 1000]", reps);
+  hipStream_t stream = (hipStream_t)hip_stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(ctx, FLLF_EDEVICE, "autotune: %s", hipGetErrorString(e));
+  }
+  // milliseconds per run with tuning t, or a negative status
+  auto timed = [&](const fllf::Tuning &t, float *ms) -> fllf_status {
+    fllf_status s2 = enqueue(ctx, plans, workspace, stream, t, nullptr);
+    if (s2 != FLLF_OK) return s2;
+    hipError_t r = hipEventRecord(e0, stream);
+    for (int i = 0; i < reps && r == hipSuccess && s2 == FLLF_OK; ++i)
+      s2 = enqueue(ctx, plans, workspace, stream, t, nullptr);
+    if (s2 != FLLF_OK) return s2;
+    if (r == hipSuccess) r = hipEventRecord(e1, stream);
+    if (r == hipSuccess) r = hipEventSynchronize(e1);
+    if (r == hipSuccess) r = hipEventElapsedTime(ms, e0, e1);
+    if (r != hipSuccess) return fail(ctx, FLLF_EDEVICE, "autotune: %s", hipGetErrorString(r));
+    *ms /= reps;
+    return FLLF_OK;
+  };
+  static const int kWaves[] = {512, 1024, 1536, 3072, 6144, 12288, 24576};
+  static const int kCaps[] = {0, 1, 2, 4};
+  fllf::Tuning best = ctx->tune;
+  float best_ms = 0.f;
+  st = timed(best, &best_ms);
+  for (int p = 0; p < fllf::kTuneParams && st == FLLF_OK; ++p) {
+    if (p == fllf::kTuneGridCap && n == 1) break;  // single jobs launch one wave per work item
+    const int *cand = p == fllf::kTuneGridCap ? kCaps : kWaves;
+    const int nc = p == fllf::kTuneGridCap ? 4 : 7;
+    for (int i = 0; i < nc && st == FLLF_OK; ++i) {
+      if (cand[i] == best.p[p]) continue;
+      fllf::Tuning t = best;
+      t.p[p] = cand[i];
+      float ms = 0.f;
+      st = timed(t, &ms);
+      if (st == FLLF_OK && ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != FLLF_OK) return st;
+  ctx->tune = best;
+  if (chosen)
+    for (int i = 0; i < fllf::kTuneParams; ++i) chosen[i] = best.p[i];
+  return FLLF_OK;
+}
+
+fllf_status fourier_llf_graph_create(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
+                                     size_t ws_bytes, fllf_graph **out) {
+  if (!out) return fail(ctx, FLLF_EINVAL, "graph_create: out is NULL");
+  *out = nullptr;
+  std::vector<fllf::JobPlan> plans;
+  fllf_status st = prepare(ctx, "graph_create", jobs, n, workspace, ws_bytes, &plans);
+  if (st != FLLF_OK) return st;
+  fllf::BatchSchedule sched;
+  hipError_t e = hipSuccess;
+  if (n > 1) {
+    fllf::build_batch(plans.data(), n, ctx->storage, (char *)workspace, ctx->tune, &sched);
+    e = hipMemcpy(workspace, sched.blob.data(), sched.table_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "graph_create: table upload: %s", hipGetErrorString(e));
+  }
+  hipStream_t cs = nullptr;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "graph_create: stream: %s", hipGetErrorString(e));
+  fllf_graph *g = new fllf_graph();
+  g->device = ctx->device;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    e = n == 1 ? fllf::launch_job(plans[0], ctx->storage, (char *)workspace, cs, nullptr, ctx->tune)
+               : fllf::launch_batch(sched, ctx->storage, (char *)workspace, cs, nullptr, ctx->tune);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    g->graph = graph;
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    fourier_llf_graph_destroy(g);
+    return fail(ctx, FLLF_EDEVICE, "graph_create: capture: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return FLLF_OK;
+}
+
+fllf_status fourier_llf_graph_launch(fllf_graph *g, void *hip_stream) {
+  if (!g || !g->exec) return fail(nullptr, FLLF_EINVAL, "graph_launch: graph is NULL");
+  hipError_t e = hipSetDevice(g->device);
+  if (e == hipSuccess) e = hipGraphLaunch(g->exec, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(nullptr, FLLF_EDEVICE, "graph_launch: %s", hipGetErrorString(e));
+  return FLLF_OK;
+}
+
+void fourier_llf_graph_destroy(fllf_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 }  // extern "C"

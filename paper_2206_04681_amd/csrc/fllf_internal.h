@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "fourier_llf.h"
 
 namespace fllf {
@@ -68,16 +70,71 @@ struct LaunchHook {
   virtual void after(hipStream_t s, const char *name, double bytes) = 0;
 };
 
-// Timing names of the per-level kernels ("down_l<l>", "up_l<l>").
+// Timing names of the per-level kernels ("down_l<l>", "up_l<l>"; "bdown_l<l>",
+// "bup_l<l>" for the batched launches).
 extern const char *const kDownNames[kMaxLevels];
 extern const char *const kUpNames[kMaxLevels];
+extern const char *const kBatchDownNames[kMaxLevels];
+extern const char *const kBatchUpNames[kMaxLevels];
+
+// Launch-shape parameters.  waves[i] is the number of waves a pass aims for when
+// it picks its segment length (the kinds: 0 = down(0), 1 = down(l >= 1),
+// 2 = up(0), 3 = up(l >= 1)); grid_cap > 0 caps a batched launch at grid_cap
+// times the blocks that fit on the device at once (a persistent launch).
+enum { kTuneDown0 = 0, kTuneDown = 1, kTuneUp0 = 2, kTuneUp = 3, kTuneGridCap = 4, kTuneParams = 5 };
+struct Tuning {
+  int p[kTuneParams];
+};
+Tuning default_tuning();
 
 // Enqueues the whole filter for one planned job on `stream`.
 hipError_t launch_job(const JobPlan &plan, fllf_storage storage, char *ws, hipStream_t stream,
-                      LaunchHook *hook);
+                      LaunchHook *hook, const Tuning &tune);
 // The same per pyramid storage type (one compilation unit each).
-hipError_t launch_job_f32(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook);
-hipError_t launch_job_f16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook);
-hipError_t launch_job_bf16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook);
+hipError_t launch_job_f32(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+hipError_t launch_job_f16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+hipError_t launch_job_bf16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+
+// ---------------------------------------------------------------------------
+// Batched form: every pass (down(l), then up(l)) of all jobs that reach level
+// l + 1 runs as one launch per kernel class (K loop, boost map, top level).
+// The per-job arguments and wave offsets of all launches form one table that
+// lives at the start of the workspace.
+// ---------------------------------------------------------------------------
+struct BatchLaunch {
+  int kind;           // 0 = down, 1 = up, 2 = copy (single-level job: in -> out)
+  int level;          // l of down(l) / up(l)
+  bool l0, map, hasd; // level-0 variant, boost map, O_{l+1} present (up)
+  int km;             // K loop length (4, 8, 16 or 32)
+  bool ex;            // K == km exactly
+  int njobs;
+  uint32_t waves;     // total waves over the jobs
+  size_t args_off;    // byte offsets of the argument array and of the njobs + 1 wave offsets
+  size_t start_off;
+  double bytes;       // algorithmic bytes of the launch
+  const void *copy_src;  // kind 2
+  void *copy_dst;
+  size_t copy_bytes;
+};
+
+struct BatchSchedule {
+  size_t table_bytes = 0;          // bytes of the table (a multiple of kAlign)
+  std::vector<unsigned char> blob; // host image of the table
+  std::vector<BatchLaunch> launches;
+};
+
+// Plans the table and the launches of n planned jobs whose workspaces follow a
+// table at byte offset 0 of ws.  Storage decides the record size.  With
+// ws == nullptr only the sizes are planned (the argument records stay zero).
+void build_batch(const JobPlan *plans, int n, fllf_storage storage, char *ws, const Tuning &tune,
+                 BatchSchedule *out);
+// Bytes the batch table of these jobs needs (0 for a single job, which uses no table).
+size_t batch_table_bytes(const JobPlan *plans, int n, fllf_storage storage);
+// Enqueues a schedule whose table is already in the workspace (ws + 0).
+hipError_t launch_batch(const BatchSchedule &s, fllf_storage storage, char *ws, hipStream_t stream,
+                        LaunchHook *hook, const Tuning &tune);
+hipError_t launch_batch_f32(const BatchSchedule &s, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+hipError_t launch_batch_f16(const BatchSchedule &s, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+hipError_t launch_batch_bf16(const BatchSchedule &s, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
 
 }  // namespace fllf

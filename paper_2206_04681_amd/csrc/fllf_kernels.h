@@ -166,17 +166,17 @@ __device__ inline void st_records_staged(char *row, int lane, int nw, const uint
         make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const int total = nw * PIECES;  // 16-byte pieces to store, record of lane 1 first
-  uint4 v[ITER];
+  // an explicitly global pointer: plain global_store_dwordx4 (not flat) even
+  // when the record plane's base was loaded from memory
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(1))) u4 gu4;
+  gu4 *dst = (gu4 *)row;
 #pragma unroll
   for (int q = 0; q < ITER; ++q) {
     const int t = min(q * 64 + lane, total - 1);
     const int r = t / PIECES + 1, part = t - (r - 1) * PIECES;
-    v[q] = *reinterpret_cast<const uint4 *>(slice + r * STRIDE + 4 * part);
-  }
-#pragma unroll
-  for (int q = 0; q < ITER; ++q) {
-    const int t = q * 64 + lane;
-    if (t < total) *reinterpret_cast<uint4 *>(row + 16u * (uint32_t)t) = v[q];
+    const u4 v = *reinterpret_cast<const u4 *>(slice + r * STRIDE + 4 * part);
+    if (q * 64 + lane < total) dst[t] = v;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -312,6 +312,30 @@ __device__ inline bool wave_coords(const Geom &g, int &lane, int &strip, int &se
   seg = __builtin_amdgcn_readfirstlane(rest % g.nsegs);
   c = __builtin_amdgcn_readfirstlane(rest / g.nsegs);
   return c < g.C;
+}
+
+// Batched launches: the waves of all jobs of one pass are numbered 0 .. total-1,
+// job j owning [start[j], start[j+1]).  A wave walks that range with a grid
+// stride, so the grid may be smaller than the work (persistent launch).
+__device__ inline uint32_t first_wave() {
+  return blockIdx.x * 4u + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// The job of wave w: the largest j with start[j] <= w (scalar binary search).
+__device__ inline int find_job(const uint32_t *__restrict__ start, int n, uint32_t w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+__device__ inline void job_coords(const Geom &g, uint32_t wv, int &strip, int &seg, int &c) {
+  strip = __builtin_amdgcn_readfirstlane((int)(wv % (uint32_t)g.nstrips));
+  const uint32_t rest = wv / (uint32_t)g.nstrips;
+  seg = __builtin_amdgcn_readfirstlane((int)(rest % (uint32_t)g.nsegs));
+  c = __builtin_amdgcn_readfirstlane((int)(rest / (uint32_t)g.nsegs));
 }
 
 // A wave touches columns outside [0, Wf) only in the first strip and in the
@@ -520,6 +544,25 @@ __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownA
   w.run();
 }
 
+template <int ST, int KM, bool EX, bool L0, bool MAP>
+__global__ void __launch_bounds__(256, min_waves_per_simd(KM))
+down_batch_kernel(const DownArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n,
+                  uint32_t total) {
+  using W = DownWave<ST, KM, EX, L0, MAP>;
+  constexpr int SLICE = W::STAGED ? staged_slice_dwords<W::NR>() : 1;
+  __shared__ uint32_t stage[4 * SLICE];
+  const int lane = threadIdx.x & 63;
+  const uint32_t stride = gridDim.x * 4u;
+  for (uint32_t w = first_wave(); w < total; w += stride) {
+    const int j = find_job(start, n, w);
+    const DownArgs &a = jobs[j];
+    int strip, seg, c;
+    job_coords(a.g, w - start[j], strip, seg, c);
+    W wv(a, lane, c, strip, seg, stage + (threadIdx.x >> 6) * SLICE);
+    wv.run();
+  }
+}
+
 // --------------------------------------------------------------------------
 // up(l)
 // --------------------------------------------------------------------------
@@ -724,6 +767,21 @@ __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs 
   w.run();
 }
 
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
+__global__ void __launch_bounds__(256, min_waves_per_simd(KM))
+up_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n, uint32_t total) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t stride = gridDim.x * 4u;
+  for (uint32_t w = first_wave(); w < total; w += stride) {
+    const int j = find_job(start, n, w);
+    const UpArgs &a = jobs[j];
+    int strip, seg, c;
+    job_coords(a.g, w - start[j], strip, seg, c);
+    UpWave<ST, KM, EX, L0, MAP, HASD> wv(a, lane, c, strip, seg);
+    wv.run();
+  }
+}
+
 // --------------------------------------------------------------------------
 // Host-side launch sequence of one job.
 // --------------------------------------------------------------------------
@@ -742,24 +800,9 @@ inline Geom make_geom(const Level &f, const Level &cl, int C, int S) {
   return g;
 }
 
-// Coarse rows per wave: long segments amortise the halo rows, short ones give
-// the 256 CUs enough waves.
 // Rows per wave segment.  Shorter segments give more waves (latency hiding,
-// fewer idle SIMDs in the last round) but re-read more halo rows.  The level-0
-// kernels read little per fine row and want many waves; the kernels that read a
-// fine level of (C, S) records want long segments.  Measured on the 4K workload.
-#ifndef FLLF_WAVES_DOWN0
-#define FLLF_WAVES_DOWN0 12288
-#endif
-#ifndef FLLF_WAVES_DOWN
-#define FLLF_WAVES_DOWN 1536
-#endif
-#ifndef FLLF_WAVES_UP0
-#define FLLF_WAVES_UP0 12288
-#endif
-#ifndef FLLF_WAVES_UP
-#define FLLF_WAVES_UP 1536
-#endif
+// fewer idle SIMDs in the last round) but re-read more halo rows; the target
+// wave count of each pass kind is a tuning parameter.
 inline int pick_segment(const Level &cl, int C, long target) {
   const long strips = (cl.w + 61) / 62;
   int S = 64;
@@ -767,78 +810,97 @@ inline int pick_segment(const Level &cl, int C, long target) {
   return S;
 }
 
-inline dim3 grid_for(const Geom &g) {
-  const long waves = (long)g.nstrips * g.nsegs * g.C;
-  return dim3((unsigned)((waves + 3) / 4), 1, 1);
+inline long geom_waves(const Geom &g) { return (long)g.nstrips * g.nsegs * g.C; }
+
+inline dim3 grid_for(const Geom &g) { return dim3((unsigned)((geom_waves(g) + 3) / 4), 1, 1); }
+
+// Arguments of down(l) / up(l) of one planned job whose workspace is ws.
+inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const Tuning &tu) {
+  const Level *lv = P.lv;
+  const int L = P.levels;
+  const bool map = P.m_map != nullptr;
+  auto M = [&](int k) -> float * {
+    if (!map) return nullptr;
+    if (k == 0) return const_cast<float *>(P.m_map);
+    return k < L - 1 ? (float *)(ws + lv[k].off_m) : nullptr;
+  };
+  DownArgs a{};
+  a.gf = l == 0 ? P.in : (const float *)(ws + lv[l].off_g);
+  a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  a.csf = l == 0 ? nullptr : (const uint32_t *)(ws + lv[l].off_cs);
+  a.csf_cs = lv[l].cs_cstride * dwp;
+  a.mf = M(l);
+  a.gc = (float *)(ws + lv[l + 1].off_g);
+  a.gc_cs = lv[l + 1].g_cstride;
+  a.csc = (uint32_t *)(ws + lv[l + 1].off_cs);
+  a.csc_cs = lv[l + 1].cs_cstride * dwp;
+  a.mc = M(l + 1);
+  a.af = l == 0 ? nullptr : (float *)(ws + lv[l].off_o);
+  a.af_cs = lv[l].g_cstride;
+  a.g = make_geom(lv[l], lv[l + 1], P.C,
+                  pick_segment(lv[l + 1], P.C, tu.p[l == 0 ? kTuneDown0 : kTuneDown]));
+  a.cf = P.coefs;
+  return a;
+}
+
+inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tuning &tu) {
+  const Level *lv = P.lv;
+  const int L = P.levels;
+  const bool map = P.m_map != nullptr;
+  UpArgs a{};
+  a.base = l == 0 ? P.in : (const float *)(ws + lv[l].off_o);
+  a.base_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  a.gf = l == 0 ? P.in : (const float *)(ws + lv[l].off_g);
+  a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  a.mf = !map ? nullptr : l == 0 ? P.m_map : (const float *)(ws + lv[l].off_m);
+  a.gc = (const float *)(ws + lv[l + 1].off_g);
+  a.gc_cs = lv[l + 1].g_cstride;
+  const bool hasd = l + 1 < L - 1;
+  a.oc = hasd ? (const float *)(ws + lv[l + 1].off_o) : nullptr;
+  a.oc_cs = lv[l + 1].g_cstride;
+  a.csc = (const uint32_t *)(ws + lv[l + 1].off_cs);
+  a.csc_cs = lv[l + 1].cs_cstride * dwp;
+  a.out = l == 0 ? P.out : (float *)(ws + lv[l].off_o);
+  a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  a.g = make_geom(lv[l], lv[l + 1], P.C, pick_segment(lv[l + 1], P.C, tu.p[l == 0 ? kTuneUp0 : kTuneUp]));
+  a.cf = P.coefs;
+  return a;
+}
+
+// Algorithmic bytes: every plane element a launch must read or write, once.
+inline double down_bytes(const JobPlan &P, int l, int dwp) {
+  const Level *lv = P.lv;
+  const double pb = 4.0 * dwp * P.K, C = P.C, mapb = P.m_map ? 4.0 : 0.0;
+  if (l == 0) return C * (4.0 * lv[0].n + (4.0 + pb) * lv[1].n) + mapb * (lv[0].n + lv[1].n);
+  return C * ((4.0 + pb + 4.0) * lv[l].n + (4.0 + pb) * lv[l + 1].n) + mapb * (lv[l].n + lv[l + 1].n);
+}
+
+inline double up_bytes(const JobPlan &P, int l, int dwp) {
+  const Level *lv = P.lv;
+  const double pb = 4.0 * dwp * P.K, C = P.C, mapb = P.m_map ? 4.0 : 0.0;
+  const bool hasd = l + 1 < P.levels - 1;
+  const double fine = l == 0 ? 4.0 : 8.0;               // I, or A_l and G_l
+  const double coarse = 4.0 + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
+  return C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n) + mapb * lv[l].n;
 }
 
 template <int ST, int KM, bool EX, bool MAP>
-hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *hook) {
+hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *hook, const Tuning &tu) {
   const int L = P.levels;
-  const int dwp = PairStore<ST>::DW;                  // dwords per pair
-  const double pb = 4.0 * dwp * P.K;                  // bytes of the K pairs per pixel
-  const double C = P.C;
+  const int dwp = PairStore<ST>::DW;  // dwords per pair
   auto pre = [&]() { if (hook) hook->before(st); };
   auto post = [&](const char *name, double bytes) { if (hook) hook->after(st, name, bytes); };
-  auto G = [&](int l) { return (float *)(ws + P.lv[l].off_g); };
-  auto CS = [&](int l) { return (uint32_t *)(ws + P.lv[l].off_cs); };
-  auto O = [&](int l) { return (float *)(ws + P.lv[l].off_o); };
-  auto M = [&](int l) -> float * {
-    if (!MAP) return nullptr;
-    if (l == 0) return const_cast<float *>(P.m_map);
-    return l < L - 1 ? (float *)(ws + P.lv[l].off_m) : nullptr;
-  };
-  const Level *lv = P.lv;
   const dim3 blk(256, 1, 1);
-  const double mapb = MAP ? 4.0 : 0.0;
-
-  // Algorithmic bytes: every plane element a launch must read or write, once.
   for (int l = 0; l + 1 < L; ++l) {
-    DownArgs a{};
-    a.gf = l == 0 ? P.in : G(l);
-    a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
-    a.csf = l == 0 ? nullptr : CS(l);
-    a.csf_cs = lv[l].cs_cstride * dwp;
-    a.mf = M(l);
-    a.gc = G(l + 1);
-    a.gc_cs = lv[l + 1].g_cstride;
-    a.csc = CS(l + 1);
-    a.csc_cs = lv[l + 1].cs_cstride * dwp;
-    a.mc = M(l + 1);
-    a.af = l == 0 ? nullptr : O(l);
-    a.af_cs = lv[l].g_cstride;
-    a.g = make_geom(lv[l], lv[l + 1], P.C,
-                    pick_segment(lv[l + 1], P.C, l == 0 ? FLLF_WAVES_DOWN0 : FLLF_WAVES_DOWN));
-    a.cf = P.coefs;
+    const DownArgs a = make_down_args(P, l, ws, dwp, tu);
     pre();
-    if (l == 0) {
-      down_kernel<ST, KM, EX, true, MAP><<<grid_for(a.g), blk, 0, st>>>(a);
-      post(kDownNames[l], C * (4.0 * lv[0].n + (4.0 + pb) * lv[1].n) + mapb * (lv[0].n + lv[1].n));
-    } else {
-      down_kernel<ST, KM, EX, false, MAP><<<grid_for(a.g), blk, 0, st>>>(a);
-      post(kDownNames[l], C * ((4.0 + pb + 4.0) * lv[l].n + (4.0 + pb) * lv[l + 1].n) +
-                              mapb * (lv[l].n + lv[l + 1].n));
-    }
+    if (l == 0) down_kernel<ST, KM, EX, true, MAP><<<grid_for(a.g), blk, 0, st>>>(a);
+    else down_kernel<ST, KM, EX, false, MAP><<<grid_for(a.g), blk, 0, st>>>(a);
+    post(kDownNames[l], down_bytes(P, l, dwp));
   }
   for (int l = L - 2; l >= 0; --l) {
-    UpArgs a{};
-    a.base = l == 0 ? P.in : O(l);
-    a.base_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
-    a.gf = l == 0 ? P.in : G(l);
-    a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
-    a.mf = M(l);
-    a.gc = G(l + 1);
-    a.gc_cs = lv[l + 1].g_cstride;
-    const bool hasd = l + 1 < L - 1;
-    a.oc = hasd ? O(l + 1) : nullptr;
-    a.oc_cs = lv[l + 1].g_cstride;
-    a.csc = CS(l + 1);
-    a.csc_cs = lv[l + 1].cs_cstride * dwp;
-    a.out = l == 0 ? P.out : O(l);
-    a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
-    a.g = make_geom(lv[l], lv[l + 1], P.C,
-                    pick_segment(lv[l + 1], P.C, l == 0 ? FLLF_WAVES_UP0 : FLLF_WAVES_UP));
-    a.cf = P.coefs;
+    const UpArgs a = make_up_args(P, l, ws, dwp, tu);
+    const bool hasd = a.oc != nullptr;
     pre();
     if (l == 0) {
       if (hasd) up_kernel<ST, KM, EX, true, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
@@ -847,29 +909,117 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
       if (hasd) up_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
       else up_kernel<ST, KM, EX, false, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
     }
-    const double fine = l == 0 ? 4.0 : 8.0;               // I, or A_l and G_l
-    const double coarse = 4.0 + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
-    post(kUpNames[l], C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n) + mapb * lv[l].n);
+    post(kUpNames[l], up_bytes(P, l, dwp));
   }
   return hipGetLastError();
 }
 
-// K == 4, 8, 16: exact loops; other K run the next larger loop with guards.
+// The K loop of a job: K == 4, 8, 16 run exact loops; other K run the next
+// larger loop with guards.
+inline void k_class(int K, int *km, bool *ex) {
+  if (K == 4 || K == 8 || K == 16) { *km = K; *ex = true; return; }
+  *ex = false;
+  *km = K < 8 ? 8 : K < 16 ? 16 : 32;
+}
+
 template <int ST>
-hipError_t launch_storage(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h) {
+hipError_t launch_storage(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
   const bool map = P.m_map != nullptr;
+  int km;
+  bool ex;
+  k_class(P.K, &km, &ex);
 #define FLLF_LAUNCH(KM, EX) \
-  return map ? launch_typed<ST, KM, EX, true>(P, ws, st, h) : launch_typed<ST, KM, EX, false>(P, ws, st, h)
-  switch (P.K) {
-    case 4: FLLF_LAUNCH(4, true);
-    case 8: FLLF_LAUNCH(8, true);
-    case 16: FLLF_LAUNCH(16, true);
-    default: break;
+  return map ? launch_typed<ST, KM, EX, true>(P, ws, st, h, tu) : launch_typed<ST, KM, EX, false>(P, ws, st, h, tu)
+  if (ex) {
+    if (km == 4) FLLF_LAUNCH(4, true);
+    if (km == 8) FLLF_LAUNCH(8, true);
+    FLLF_LAUNCH(16, true);
   }
-  if (P.K < 8) FLLF_LAUNCH(8, false);
-  if (P.K < 16) FLLF_LAUNCH(16, false);
+  if (km == 8) FLLF_LAUNCH(8, false);
+  if (km == 16) FLLF_LAUNCH(16, false);
   FLLF_LAUNCH(32, false);
 #undef FLLF_LAUNCH
+}
+
+// --------------------------------------------------------------------------
+// Batched launches
+// --------------------------------------------------------------------------
+// Blocks of 256 threads of `kernel` that fit on the device at once.
+inline long resident_blocks(const void *kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess) return 0;
+  return (long)cus * per_cu;
+}
+
+inline dim3 batch_grid(const BatchLaunch &b, const void *kernel, const Tuning &tu) {
+  long blocks = ((long)b.waves + 3) / 4;
+  if (tu.p[kTuneGridCap] > 0) {
+    const long cap = resident_blocks(kernel) * tu.p[kTuneGridCap];
+    if (cap > 0 && cap < blocks) blocks = cap;
+  }
+  return dim3((unsigned)blocks, 1, 1);
+}
+
+template <int ST, int KM, bool EX, bool MAP>
+hipError_t launch_batch_typed(const BatchLaunch &b, char *ws, hipStream_t st, const Tuning &tu) {
+  const dim3 blk(256, 1, 1);
+  const uint32_t *start = (const uint32_t *)(ws + b.start_off);
+  if (b.kind == 0) {
+    const DownArgs *args = (const DownArgs *)(ws + b.args_off);
+#define FLLF_DOWN(L0)                                                                   \
+  {                                                                                     \
+    auto k = down_batch_kernel<ST, KM, EX, L0, MAP>;                                    \
+    k<<<batch_grid(b, (const void *)k, tu), blk, 0, st>>>(args, start, b.njobs, b.waves); \
+  }
+    if (b.l0) FLLF_DOWN(true) else FLLF_DOWN(false)
+#undef FLLF_DOWN
+  } else {
+    const UpArgs *args = (const UpArgs *)(ws + b.args_off);
+#define FLLF_UP(L0, HASD)                                                               \
+  {                                                                                     \
+    auto k = up_batch_kernel<ST, KM, EX, L0, MAP, HASD>;                                \
+    k<<<batch_grid(b, (const void *)k, tu), blk, 0, st>>>(args, start, b.njobs, b.waves); \
+  }
+    if (b.l0) {
+      if (b.hasd) FLLF_UP(true, true) else FLLF_UP(true, false)
+    } else {
+      if (b.hasd) FLLF_UP(false, true) else FLLF_UP(false, false)
+    }
+#undef FLLF_UP
+  }
+  return hipGetLastError();
+}
+
+template <int ST>
+hipError_t launch_batch_storage(const BatchSchedule &s, char *ws, hipStream_t st, LaunchHook *hook,
+                                const Tuning &tu) {
+  for (const BatchLaunch &b : s.launches) {
+    if (hook) hook->before(st);
+    hipError_t e = hipSuccess;
+    if (b.kind == 2) {
+      e = hipMemcpyAsync(b.copy_dst, b.copy_src, b.copy_bytes, hipMemcpyDeviceToDevice, st);
+    } else {
+#define FLLF_B(KM, EX) \
+  e = b.map ? launch_batch_typed<ST, KM, EX, true>(b, ws, st, tu) : launch_batch_typed<ST, KM, EX, false>(b, ws, st, tu)
+      if (b.ex) {
+        if (b.km == 4) FLLF_B(4, true);
+        else if (b.km == 8) FLLF_B(8, true);
+        else FLLF_B(16, true);
+      } else {
+        if (b.km == 8) FLLF_B(8, false);
+        else if (b.km == 16) FLLF_B(16, false);
+        else FLLF_B(32, false);
+      }
+#undef FLLF_B
+    }
+    if (e != hipSuccess) return e;
+    if (hook)
+      hook->after(st, b.kind == 0 ? kBatchDownNames[b.level] : b.kind == 1 ? kBatchUpNames[b.level] : "copy",
+                  b.bytes);
+  }
+  return hipSuccess;
 }
 
 }  // namespace fllf

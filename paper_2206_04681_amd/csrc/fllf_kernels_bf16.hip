@@ -3,8 +3,12 @@
 
 namespace fllf {
 
-hipError_t launch_job_bf16(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h) {
-  return launch_storage<FLLF_STORE_BF16>(P, ws, st, h);
+hipError_t launch_job_bf16(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
+  return launch_storage<FLLF_STORE_BF16>(P, ws, st, h, tu);
+}
+
+hipError_t launch_batch_bf16(const BatchSchedule &s, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
+  return launch_batch_storage<FLLF_STORE_BF16>(s, ws, st, h, tu);
 }
 
 }  // namespace fllf

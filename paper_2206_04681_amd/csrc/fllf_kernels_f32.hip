@@ -3,8 +3,12 @@
 
 namespace fllf {
 
-hipError_t launch_job_f32(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h) {
-  return launch_storage<FLLF_STORE_F32>(P, ws, st, h);
+hipError_t launch_job_f32(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
+  return launch_storage<FLLF_STORE_F32>(P, ws, st, h, tu);
+}
+
+hipError_t launch_batch_f32(const BatchSchedule &s, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
+  return launch_batch_storage<FLLF_STORE_F32>(s, ws, st, h, tu);
 }
 
 }  // namespace fllf

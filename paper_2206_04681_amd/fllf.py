@@ -26,7 +26,12 @@ STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run",
             "fourier_llf_destroy", "fourier_llf_last_error", "fourier_llf_fit",
             "fourier_llf_max_levels", "fourier_llf_validate", "fourier_llf_footprint",
-            "fourier_llf_version", "fourier_llf_timing_enable", "fourier_llf_timing_read")
+            "fourier_llf_version", "fourier_llf_timing_enable", "fourier_llf_timing_read",
+            "fourier_llf_set_tuning", "fourier_llf_get_tuning", "fourier_llf_autotune",
+            "fourier_llf_graph_create", "fourier_llf_graph_launch", "fourier_llf_graph_destroy")
+
+# Launch-shape parameters (FLLF_TUNE_*): target waves of the four pass kinds, grid cap.
+TUNE_NAMES = ("down0", "down", "up0", "up", "grid_cap")
 
 
 class FourierLLFError(RuntimeError):
@@ -97,6 +102,19 @@ def lib() -> ctypes.CDLL:
         L.fourier_llf_timing_read.restype = i32
         L.fourier_llf_version.argtypes = []
         L.fourier_llf_version.restype = i32
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.fourier_llf_set_tuning.argtypes = [vp, ip]
+        L.fourier_llf_set_tuning.restype = i32
+        L.fourier_llf_get_tuning.argtypes = [vp, ip]
+        L.fourier_llf_get_tuning.restype = i32
+        L.fourier_llf_autotune.argtypes = [vp, jp, i32, vp, sz, vp, i32, ip]
+        L.fourier_llf_autotune.restype = i32
+        L.fourier_llf_graph_create.argtypes = [vp, jp, i32, vp, sz, ctypes.POINTER(vp)]
+        L.fourier_llf_graph_create.restype = i32
+        L.fourier_llf_graph_launch.argtypes = [vp, vp]
+        L.fourier_llf_graph_launch.restype = i32
+        L.fourier_llf_graph_destroy.argtypes = [vp]
+        L.fourier_llf_graph_destroy.restype = None
         _LIB = L
     return _LIB
 
@@ -255,11 +273,51 @@ class FourierLLF:
 
     def timing_read(self) -> List[dict]:
         """Per kernel class: launches, total ms and algorithmic bytes since the last read."""
-        buf = (FllfKernelTime * 16)()
+        cap = 128
+        buf = (FllfKernelTime * cap)()
         n = ctypes.c_int()
-        _check(lib().fourier_llf_timing_read(self._ctx, buf, 16, ctypes.byref(n)), self._ctx)
+        _check(lib().fourier_llf_timing_read(self._ctx, buf, cap, ctypes.byref(n)), self._ctx)
         return [dict(name=buf[i].name.decode(), launches=buf[i].launches, total_ms=buf[i].total_ms,
-                     bytes=buf[i].bytes) for i in range(min(n.value, 16))]
+                     bytes=buf[i].bytes) for i in range(min(n.value, cap))]
+
+    # -- launch shape ----------------------------------------------------------
+    def set_tuning(self, params: Optional[Sequence[int]] = None) -> None:
+        """Set (FLLF_TUNE_*) launch-shape parameters; None restores the built-in ones."""
+        if params is None:
+            _check(lib().fourier_llf_set_tuning(self._ctx, None), self._ctx)
+            return
+        arr = (ctypes.c_int32 * len(TUNE_NAMES))(*[int(v) for v in params])
+        _check(lib().fourier_llf_set_tuning(self._ctx, arr), self._ctx)
+
+    def get_tuning(self) -> List[int]:
+        arr = (ctypes.c_int32 * len(TUNE_NAMES))()
+        _check(lib().fourier_llf_get_tuning(self._ctx, arr), self._ctx)
+        return list(arr)
+
+    def autotune(self, fjobs: Sequence[FllfJob], workspace=None, stream=None, reps: int = 3) -> List[int]:
+        """Time candidate launch shapes on these jobs and keep the fastest (synchronous)."""
+        import torch
+        arr = _job_array(fjobs)
+        ws = workspace if workspace is not None else self.workspace(self.workspace_size(fjobs))
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        out = (ctypes.c_int32 * len(TUNE_NAMES))()
+        _check(lib().fourier_llf_autotune(self._ctx, arr, len(fjobs), ws.data_ptr(), ws.numel(), sptr,
+                                          int(reps), out), self._ctx)
+        return list(out)
+
+    def graph(self, fjobs: Sequence[FllfJob], workspace=None) -> "Graph":
+        """Capture the launches of these jobs into a replayable HIP graph with its own workspace."""
+        import torch
+        need = self.workspace_size(fjobs)
+        ws = workspace if workspace is not None else torch.empty(max(need, 256), dtype=torch.uint8,
+                                                                 device=self.device)
+        arr = _job_array(fjobs)
+        g = ctypes.c_void_p()
+        _check(lib().fourier_llf_graph_create(self._ctx, arr, len(fjobs), ws.data_ptr(), ws.numel(),
+                                              ctypes.byref(g)), self._ctx)
+        return Graph(g, ws)
 
     def run(self, x, levels: int, sigma_r: float, m: float, K: int, R: float = 1.0, T: float = 0.0,
             out=None, m_map=None, stream=None):
@@ -273,3 +331,29 @@ class FourierLLF:
         prepared = [self._prepare(j) for j in jobs]
         self.run_jobs([p[0] for p in prepared], stream=stream)
         return [p[1] for p in prepared]
+
+
+class Graph:
+    """A captured schedule (``fllf_graph``); keeps its workspace alive."""
+
+    def __init__(self, handle, workspace):
+        self._g = handle
+        self.workspace = workspace
+
+    def launch(self, stream=None) -> None:
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.workspace.device)
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().fourier_llf_graph_launch(self._g, sptr))
+
+    def close(self) -> None:
+        if getattr(self, "_g", None):
+            lib().fourier_llf_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

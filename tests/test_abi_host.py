@@ -70,7 +70,15 @@ def _job(F, **kw):
 
 def test_validate_accepts_good_job(F):
     assert F.validate([_job(F)]) == F.FLLF_OK
-    assert F.validate([_job(F), _job(F, width=3, height=2, levels=2, K=32)], "bf16") == F.FLLF_OK
+    other = dict(in_ptr=0x200000000, out_ptr=0x300000000)
+    assert F.validate([_job(F), _job(F, width=3, height=2, levels=2, K=32, **other)], "bf16") == F.FLLF_OK
+
+
+def test_validate_rejects_batch_overlap(F):
+    # a batch where one job writes into another job's input or output
+    assert F.validate([_job(F), _job(F, in_ptr=0x200000000)]) == F.FLLF_EINVAL
+    assert "overlaps" in F.last_error()
+    assert F.validate([_job(F), _job(F, out_ptr=0x200000000, in_ptr=0x100000000 + 64)]) == F.FLLF_EINVAL
 
 
 @pytest.mark.parametrize("bad", [
@@ -105,9 +113,13 @@ def _expected_footprint(w, h, C, L, K, pair_bytes, has_map=False):
 def test_footprint_matches_layout(F, storage, pb):
     j = _job(F, width=3840, height=2160, channels=3, levels=8, K=8)
     assert F.footprint([j], storage) == _expected_footprint(3840, 2160, 3, 8, 8, pb)
-    j2 = _job(F, width=1001, height=777, channels=1, levels=5, K=3, m_map_ptr=0x5000)
-    assert F.footprint([j, j2], storage) == (_expected_footprint(3840, 2160, 3, 8, 8, pb)
+    j2 = _job(F, width=1001, height=777, channels=1, levels=5, K=3, m_map_ptr=0x5000,
+              in_ptr=0x200000000, out_ptr=0x300000000)
+    assert F.footprint([j2], storage) == _expected_footprint(1001, 777, 1, 5, 3, pb, True)
+    # two jobs: both workspaces plus the batch launch table in front of them
+    table = F.footprint([j, j2], storage) - (_expected_footprint(3840, 2160, 3, 8, 8, pb)
                                              + _expected_footprint(1001, 777, 1, 5, 3, pb, True))
+    assert table > 0 and table % 256 == 0 and table < 2 * 32 * 1024
 
 
 def test_footprint_of_4k_rgb_k8(F):
