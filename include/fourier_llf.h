@@ -160,6 +160,68 @@ void fourier_llf_destroy(fllf_ctx *ctx);
  * (ctx may be NULL).  The string stays valid until the next call on this thread. */
 const char *fourier_llf_last_error(const fllf_ctx *ctx);
 
+/* ---- serving: continuous batching over a device arena --------------------- */
+
+/* A server runs many independent jobs that arrive over time.  Each job is the
+ * same filter as fourier_llf_run (same result bit for bit); what differs is
+ * the schedule.  Every fourier_llf_server_step
+ *   1. admits queued jobs in arrival order while their workspace fits in the
+ *      arena (first fit; admission stops at the first job that does not fit,
+ *      so no job is overtaken) and while fewer than max_active are in flight;
+ *   2. enqueues the next pass of every admitted job -- REDUCE to level l + 1 or
+ *      product-sum and collapse at level l -- as batched launches, passes of
+ *      the same kernel class sharing one launch whatever their job or level
+ *      (iteration-level batching: jobs join and leave between passes).
+ * A job's workspace returns to the arena once its last pass has completed on
+ * the device (seen by step or poll).  Everything runs on the stream given to
+ * step.  The arena is a caller-owned device buffer; it bounds the device
+ * memory the server uses beyond the jobs' own input and output images.  A
+ * server is not thread-safe. */
+typedef struct fllf_server fllf_server; /* opaque */
+
+typedef struct {
+  int32_t queued;       /* submitted, not yet admitted */
+  int32_t active;       /* admitted, with passes left to enqueue */
+  int32_t finishing;    /* all passes enqueued, completion not yet seen */
+  int32_t max_active;
+  int64_t steps;        /* steps that enqueued work */
+  int64_t launches;     /* kernel launches and copies enqueued */
+  int64_t completed;    /* jobs reported by fourier_llf_server_poll */
+  uint64_t arena_bytes; /* bytes available to job workspaces */
+  uint64_t arena_used;  /* bytes held by admitted jobs now */
+  uint64_t arena_peak;  /* largest arena_used so far */
+} fllf_server_stats;
+
+/* Create a server over `arena` (device, 256-byte aligned, arena_bytes long,
+ * owned by the caller and used by nothing else while the server lives) for a
+ * context.  At most max_active (1..4096) jobs are in flight at once; a few
+ * tables of launch arguments are carved from the front of the arena. */
+fllf_status fourier_llf_server_create(fllf_ctx *ctx, void *arena, size_t arena_bytes, int max_active,
+                                      fllf_server **out);
+
+/* Queue one job (validated now).  `tag` identifies it in fourier_llf_server_poll.
+ * `ready_event` (a hipEvent_t, may be NULL) marks the job's input as written,
+ * e.g. the end of its upload on another stream: its first pass waits for it on
+ * the device.  FLLF_ENOMEM if its workspace exceeds what the arena can ever
+ * hold.  in/out must stay valid until the job is reported done. */
+fllf_status fourier_llf_server_submit(fllf_server *srv, const fllf_job *job, uint64_t tag,
+                                      void *ready_event);
+
+/* Admit and enqueue one pass of every admitted job on `hip_stream` (see above).
+ * Sets *pending (may be NULL) to the number of jobs not yet reported done.
+ * Does not wait for the device, except when the ring of launch tables is full
+ * (the table of the step four steps back must have been consumed). */
+fllf_status fourier_llf_server_step(fllf_server *srv, void *hip_stream, int *pending);
+
+/* Non-blocking: write the tags of up to max jobs whose output is ready (in
+ * completion order) to tags[] and their number to *n; releases their workspace. */
+fllf_status fourier_llf_server_poll(fllf_server *srv, uint64_t *tags, int max, int *n);
+
+fllf_status fourier_llf_server_stats(const fllf_server *srv, fllf_server_stats *out);
+
+/* Release the server.  NULL-safe; waits for the work it enqueued. */
+void fourier_llf_server_destroy(fllf_server *srv);
+
 /* ---- kernel timing (benchmarks) ------------------------------------------ */
 
 /* Aggregated device time of one kernel class over the launches recorded since

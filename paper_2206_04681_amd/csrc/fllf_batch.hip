@@ -11,6 +11,9 @@
 // The launches find their jobs in a table at the start of the workspace: per
 // launch, the argument records of its jobs and the prefix sums of their wave
 // counts (a wave finds its job by binary search).
+//
+// A serving step uses the same launches for independent passes of different
+// jobs: passes of one kernel class share a launch whatever their level.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -51,82 +54,115 @@ uint32_t pass_waves(const JobPlan &P, int l, bool down, const Tuning &tu) {
   return (uint32_t)geom_waves(g);
 }
 
-// Class of a job's launch: (K loop, exact, map, has O_{l+1}).
-typedef std::tuple<int, bool, bool, bool> ClassKey;
-
-}  // namespace
-
-void build_batch(const JobPlan *P, int n, fllf_storage storage, char *ws, const Tuning &tu, BatchSchedule *out) {
-  out->launches.clear();
-  out->blob.clear();
-  const int dwp = pair_dwords(storage);
-  int maxL = 1;
-  for (int j = 0; j < n; ++j) maxL = std::max(maxL, P[j].levels);
-  size_t off = 0;
+// Appends to the table `out->blob` (growing it) one launch per kernel class of
+// the given (job, pass) items.  Items of one class may be at different levels:
+// down(l >= 1) passes of any level share a kernel, as do up(l >= 1) passes.
+void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning &tu, BatchSchedule *out) {
+  size_t off = out->blob.size();
   auto reserve = [&](size_t bytes) {
     const size_t at = off;
     off = align_up(off + bytes);
     out->blob.resize(off, 0);
     return at;
   };
-  for (int j = 0; j < n; ++j) {
-    if (P[j].levels != 1) continue;
+  // (kind, level-0 pass, K loop, exact, map, has O_{l+1})
+  typedef std::tuple<int, bool, int, bool, bool, bool> Key;
+  std::map<Key, std::vector<int>> groups;
+  for (int i = 0; i < n; ++i) {
+    const PassItem &it = items[i];
+    if (it.P->levels == 1) {
+      BatchLaunch b{};
+      b.kind = 2;
+      b.copy_src = it.P->in;
+      b.copy_dst = it.P->out;
+      b.copy_bytes = it.P->lv[0].n * it.P->C * sizeof(float);
+      b.bytes = 2.0 * b.copy_bytes;
+      out->launches.push_back(b);
+      continue;
+    }
+    int km;
+    bool ex;
+    k_class(it.P->K, &km, &ex);
+    const bool hasd = !it.down && it.l + 1 < it.P->levels - 1;
+    groups[Key(it.down ? 0 : 1, it.l == 0, km, ex, it.P->m_map != nullptr, hasd)].push_back(i);
+  }
+  for (auto &kv : groups) {
+    const std::vector<int> &is = kv.second;
     BatchLaunch b{};
-    b.kind = 2;
-    b.copy_src = P[j].in;
-    b.copy_dst = P[j].out;
-    b.copy_bytes = P[j].lv[0].n * P[j].C * sizeof(float);
-    b.bytes = 2.0 * b.copy_bytes;
+    b.kind = std::get<0>(kv.first);
+    const bool down = b.kind == 0;
+    b.l0 = std::get<1>(kv.first);
+    b.km = std::get<2>(kv.first);
+    b.ex = std::get<3>(kv.first);
+    b.map = std::get<4>(kv.first);
+    b.hasd = std::get<5>(kv.first);
+    b.level = items[is[0]].l;  // the finest level of the group names the launch
+    for (int i : is) b.level = std::min(b.level, items[i].l);
+    b.njobs = (int)is.size();
+    const size_t rec = down ? sizeof(DownArgs) : sizeof(UpArgs);
+    b.args_off = reserve(rec * is.size());
+    b.start_off = reserve(sizeof(uint32_t) * (is.size() + 1));
+    uint32_t total = 0;
+    for (size_t q = 0; q < is.size(); ++q) {
+      const PassItem &it = items[is[q]];
+      std::memcpy(out->blob.data() + b.start_off + 4 * q, &total, 4);
+      total += pass_waves(*it.P, it.l, down, tu);
+      b.bytes += down ? down_bytes(*it.P, it.l, dwp) : up_bytes(*it.P, it.l, dwp);
+      if (ws) {
+        if (down) {
+          const DownArgs a = make_down_args(*it.P, it.l, ws, dwp, tu);
+          std::memcpy(out->blob.data() + b.args_off + rec * q, &a, rec);
+        } else {
+          const UpArgs a = make_up_args(*it.P, it.l, ws, dwp, tu);
+          std::memcpy(out->blob.data() + b.args_off + rec * q, &a, rec);
+        }
+      }
+    }
+    std::memcpy(out->blob.data() + b.start_off + 4 * is.size(), &total, 4);
+    b.waves = total;
     out->launches.push_back(b);
   }
+  out->table_bytes = off;
+}
+
+}  // namespace
+
+void build_step(const PassItem *items, int n, fllf_storage storage, char *ws, const Tuning &tu,
+                BatchSchedule *out) {
+  out->launches.clear();
+  out->blob.clear();
+  add_launches(items, n, pair_dwords(storage), ws, tu, out);
+}
+
+void build_batch(const JobPlan *P, int n, fllf_storage storage, char *ws, const Tuning &tu, BatchSchedule *out) {
+  out->launches.clear();
+  out->blob.clear();
+  out->table_bytes = 0;
+  const int dwp = pair_dwords(storage);
+  int maxL = 1;
+  std::vector<PassItem> items;
+  for (int j = 0; j < n; ++j) {
+    maxL = std::max(maxL, P[j].levels);
+    if (P[j].levels == 1) items.push_back(PassItem{&P[j], 0, true});
+  }
+  add_launches(items.data(), (int)items.size(), dwp, ws, tu, out);
+  // passes aligned on the level index: every job's down passes before its up passes
   for (int pass = 0; pass < 2 * (maxL - 1); ++pass) {
     const bool down = pass < maxL - 1;
     const int l = down ? pass : 2 * (maxL - 1) - 1 - pass;
-    std::map<ClassKey, std::vector<int>> groups;
-    for (int j = 0; j < n; ++j) {
-      if (l + 1 >= P[j].levels) continue;
-      int km;
-      bool ex;
-      k_class(P[j].K, &km, &ex);
-      const bool hasd = !down && l + 1 < P[j].levels - 1;
-      groups[ClassKey(km, ex, P[j].m_map != nullptr, hasd)].push_back(j);
-    }
-    for (auto &kv : groups) {
-      const std::vector<int> &js = kv.second;
-      BatchLaunch b{};
-      b.kind = down ? 0 : 1;
-      b.level = l;
-      b.l0 = l == 0;
-      b.km = std::get<0>(kv.first);
-      b.ex = std::get<1>(kv.first);
-      b.map = std::get<2>(kv.first);
-      b.hasd = std::get<3>(kv.first);
-      b.njobs = (int)js.size();
-      const size_t rec = down ? sizeof(DownArgs) : sizeof(UpArgs);
-      b.args_off = reserve(rec * js.size());
-      b.start_off = reserve(sizeof(uint32_t) * (js.size() + 1));
-      uint32_t total = 0;
-      for (size_t i = 0; i < js.size(); ++i) {
-        const JobPlan &J = P[js[i]];
-        std::memcpy(out->blob.data() + b.start_off + 4 * i, &total, 4);
-        total += pass_waves(J, l, down, tu);
-        b.bytes += down ? down_bytes(J, l, dwp) : up_bytes(J, l, dwp);
-        if (ws) {
-          if (down) {
-            const DownArgs a = make_down_args(J, l, ws, dwp, tu);
-            std::memcpy(out->blob.data() + b.args_off + rec * i, &a, rec);
-          } else {
-            const UpArgs a = make_up_args(J, l, ws, dwp, tu);
-            std::memcpy(out->blob.data() + b.args_off + rec * i, &a, rec);
-          }
-        }
-      }
-      std::memcpy(out->blob.data() + b.start_off + 4 * js.size(), &total, 4);
-      b.waves = total;
-      out->launches.push_back(b);
-    }
+    items.clear();
+    for (int j = 0; j < n; ++j)
+      if (l + 1 < P[j].levels) items.push_back(PassItem{&P[j], l, down});
+    add_launches(items.data(), (int)items.size(), dwp, ws, tu, out);
   }
-  out->table_bytes = off;
+}
+
+size_t step_table_bound(int n) {
+  // per launch group: the records and n_g + 1 offsets, each padded to kAlign;
+  // at most 2 kinds x 2 level-0 flags x 6 K loops x 2 maps x 2 top flags groups
+  const size_t groups = 96;
+  const size_t rec = std::max(sizeof(DownArgs), sizeof(UpArgs));
+  return align_up(rec * (size_t)n + 4 * (size_t)n + groups * (4 + 2 * (kAlign - 1)));
 }
 
 size_t batch_table_bytes(const JobPlan *plans, int n, fllf_storage storage) {

@@ -314,6 +314,32 @@ static fllf_status validate(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_sto
   return FLLF_OK;
 }
 
+}  // extern "C"
+
+namespace fllf {
+
+fllf_storage ctx_storage(const fllf_ctx *ctx) { return ctx->storage; }
+int ctx_device(const fllf_ctx *ctx) { return ctx->device; }
+const Tuning &ctx_tuning(const fllf_ctx *ctx) { return ctx->tune; }
+LaunchHook *ctx_hook(fllf_ctx *ctx) { return ctx->timer; }
+
+fllf_status ctx_fail(fllf_ctx *ctx, fllf_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  return fail(ctx, st, "%s", buf);
+}
+
+fllf_status validate_jobs(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_storage storage) {
+  return validate(ctx, jobs, n, storage);
+}
+
+}  // namespace fllf
+
+extern "C" {
+
 fllf_status fourier_llf_validate(const fllf_job *jobs, int n, fllf_storage storage) {
   return validate(nullptr, jobs, n, storage);
 }

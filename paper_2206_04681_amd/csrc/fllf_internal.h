@@ -128,6 +128,18 @@ struct BatchSchedule {
 // ws == nullptr only the sizes are planned (the argument records stay zero).
 void build_batch(const JobPlan *plans, int n, fllf_storage storage, char *ws, const Tuning &tune,
                  BatchSchedule *out);
+// One pass of one job: down(l) or up(l).
+struct PassItem {
+  const JobPlan *P;
+  int l;
+  bool down;
+};
+// The launches of independent passes of different jobs (one serving step): one
+// launch per kernel class, levels mixed; the table starts at byte 0 of the blob.
+void build_step(const PassItem *items, int n, fllf_storage storage, char *ws, const Tuning &tune,
+                BatchSchedule *out);
+// Upper bound of build_step's table bytes for n items.
+size_t step_table_bound(int n);
 // Bytes the batch table of these jobs needs (0 for a single job, which uses no table).
 size_t batch_table_bytes(const JobPlan *plans, int n, fllf_storage storage);
 // Enqueues a schedule whose table is already in the workspace (ws + 0).
@@ -136,5 +148,17 @@ hipError_t launch_batch(const BatchSchedule &s, fllf_storage storage, char *ws, 
 hipError_t launch_batch_f32(const BatchSchedule &s, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
 hipError_t launch_batch_f16(const BatchSchedule &s, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
 hipError_t launch_batch_bf16(const BatchSchedule &s, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+
+// ---------------------------------------------------------------------------
+// Context access for the other host units (the context is defined in fllf_host.cpp).
+// ---------------------------------------------------------------------------
+fllf_storage ctx_storage(const fllf_ctx *ctx);
+int ctx_device(const fllf_ctx *ctx);
+const Tuning &ctx_tuning(const fllf_ctx *ctx);
+LaunchHook *ctx_hook(fllf_ctx *ctx);
+// Records the message as the thread's (and the context's) last error; returns st.
+fllf_status ctx_fail(fllf_ctx *ctx, fllf_status st, const char *fmt, ...);
+// The parameter checks of fourier_llf_run.
+fllf_status validate_jobs(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_storage storage);
 
 }  // namespace fllf

@@ -28,7 +28,9 @@ EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run
             "fourier_llf_max_levels", "fourier_llf_validate", "fourier_llf_footprint",
             "fourier_llf_version", "fourier_llf_timing_enable", "fourier_llf_timing_read",
             "fourier_llf_set_tuning", "fourier_llf_get_tuning", "fourier_llf_autotune",
-            "fourier_llf_graph_create", "fourier_llf_graph_launch", "fourier_llf_graph_destroy")
+            "fourier_llf_graph_create", "fourier_llf_graph_launch", "fourier_llf_graph_destroy",
+            "fourier_llf_server_create", "fourier_llf_server_submit", "fourier_llf_server_step",
+            "fourier_llf_server_poll", "fourier_llf_server_stats", "fourier_llf_server_destroy")
 
 # Launch-shape parameters (FLLF_TUNE_*): target waves of the four pass kinds, grid cap.
 TUNE_NAMES = ("down0", "down", "up0", "up", "grid_cap")
@@ -63,6 +65,14 @@ class FllfJob(ctypes.Structure):
         ("period_T", ctypes.c_double),
         ("m_map", ctypes.c_void_p),
     ]
+
+
+class FllfServerStats(ctypes.Structure):
+    """Mirror of ``fllf_server_stats``."""
+    _fields_ = [("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("finishing", ctypes.c_int32),
+                ("max_active", ctypes.c_int32), ("steps", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64)]
 
 
 _LIB = None
@@ -115,6 +125,19 @@ def lib() -> ctypes.CDLL:
         L.fourier_llf_graph_launch.restype = i32
         L.fourier_llf_graph_destroy.argtypes = [vp]
         L.fourier_llf_graph_destroy.restype = None
+        u64 = ctypes.c_uint64
+        L.fourier_llf_server_create.argtypes = [vp, vp, sz, i32, ctypes.POINTER(vp)]
+        L.fourier_llf_server_create.restype = i32
+        L.fourier_llf_server_submit.argtypes = [vp, jp, u64, vp]
+        L.fourier_llf_server_submit.restype = i32
+        L.fourier_llf_server_step.argtypes = [vp, vp, ctypes.POINTER(i32)]
+        L.fourier_llf_server_step.restype = i32
+        L.fourier_llf_server_poll.argtypes = [vp, ctypes.POINTER(u64), i32, ctypes.POINTER(i32)]
+        L.fourier_llf_server_poll.restype = i32
+        L.fourier_llf_server_stats.argtypes = [vp, ctypes.POINTER(FllfServerStats)]
+        L.fourier_llf_server_stats.restype = i32
+        L.fourier_llf_server_destroy.argtypes = [vp]
+        L.fourier_llf_server_destroy.restype = None
         _LIB = L
     return _LIB
 
@@ -351,6 +374,67 @@ class Graph:
         if getattr(self, "_g", None):
             lib().fourier_llf_graph_destroy(self._g)
             self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server (``fllf_server``) over a device arena of
+    `arena_bytes` taken from torch.  Jobs are marshalled like FourierLLF.run;
+    scheduling, admission and launches happen in the library."""
+
+    def __init__(self, llf: FourierLLF, arena_bytes: int, max_active: int = 64):
+        import torch
+        self.llf = llf
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=llf.device)
+        h = ctypes.c_void_p()
+        _check(lib().fourier_llf_server_create(llf._ctx, self.arena.data_ptr(), self.arena.numel(),
+                                               int(max_active), ctypes.byref(h)), llf._ctx)
+        self._s = h
+        self._keep = {}  # tag -> tensors that must outlive the job
+
+    def submit(self, job: Job, tag: int, ready_event=None):
+        """Queue a job; returns its output tensor (valid once `tag` is polled).
+        `ready_event`: a torch.cuda.Event recorded after the input was written."""
+        fj, out = self.llf._prepare(job)
+        ev = ready_event.cuda_event if ready_event is not None else None
+        _check(lib().fourier_llf_server_submit(self._s, ctypes.byref(fj), int(tag), ev), self.llf._ctx)
+        self._keep[int(tag)] = (job, out, ready_event)
+        return out
+
+    def step(self, stream=None) -> int:
+        """Admit and enqueue one pass of every admitted job; returns jobs not yet reported."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.llf.device)
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        pending = ctypes.c_int32()
+        _check(lib().fourier_llf_server_step(self._s, sptr, ctypes.byref(pending)), self.llf._ctx)
+        return int(pending.value)
+
+    def poll(self, max_n: int = 256) -> List[int]:
+        """Tags of jobs whose output is ready (non-blocking)."""
+        buf = (ctypes.c_uint64 * max_n)()
+        n = ctypes.c_int32()
+        _check(lib().fourier_llf_server_poll(self._s, buf, max_n, ctypes.byref(n)), self.llf._ctx)
+        tags = [int(buf[i]) for i in range(n.value)]
+        for t in tags:
+            self._keep.pop(t, None)
+        return tags
+
+    def stats(self) -> dict:
+        st = FllfServerStats()
+        _check(lib().fourier_llf_server_stats(self._s, ctypes.byref(st)), self.llf._ctx)
+        return {name: getattr(st, name) for name, _ in FllfServerStats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_s", None):
+            lib().fourier_llf_server_destroy(self._s)
+            self._s = None
 
     def __del__(self):
         try:

@@ -117,3 +117,39 @@ def batch_workloads(n: int = 64, seed: int = 3, K: int = 8, m: float = 2.0) -> L
     sig = rng.uniform(0.05, 0.3, size=n)
     return [Workload(int(H[i]), int(W[i]), int(ch[i]), levels_for_size(int(H[i]), int(W[i])),
                      K, float(sig[i]), m, seed=1000 * seed + i) for i in range(n)]
+
+
+# Request stream of the serving form: RGB sizes with their probabilities.
+SERVE_SIZES = ((720, 1280), (1080, 1920), (2160, 3840), (4320, 7680))
+SERVE_WEIGHTS = (0.4, 0.3, 0.25, 0.05)
+
+
+@dataclass(frozen=True)
+class Request:
+    """One request of the serving form: arrival time (s) and its job."""
+    arrival: float
+    work: Workload
+
+
+def serve_requests(rate: float = 200.0, seconds: float = 60.0, seed: int = 4, m: float = 2.0,
+                   sizes=SERVE_SIZES, weights=SERVE_WEIGHTS, Ks=(4, 8, 16),
+                   content_variants: int = 4) -> List[Request]:
+    """Open-loop Poisson arrivals at `rate` per second for `seconds`: RGB sizes
+    drawn with `weights`, K uniform over `Ks`, sigma_r ~ U[0.05, 0.3], levels by
+    size (levels_for_size).  Image content cycles through `content_variants`
+    seeds per size (the content does not change the work)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t, out = 0.0, []
+    p = np.asarray(weights, dtype=np.float64)
+    p = p / p.sum()
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        h, w = sizes[int(rng.choice(len(sizes), p=p))]
+        K = int(Ks[int(rng.integers(0, len(Ks)))])
+        sig = float(rng.uniform(0.05, 0.3))
+        variant = int(rng.integers(0, content_variants))
+        out.append(Request(t, Workload(h, w, 3, levels_for_size(h, w), K, sig, m,
+                                       seed=100000 * seed + 1000 * variant + h % 997)))
+    return out
