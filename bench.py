@@ -8,6 +8,16 @@ per-level product-sum and the collapse) with the input already resident in HBM.
 The headline value uses float32 pyramid storage; the float16- and
 bfloat16-storage forms are reported beside it.
 
+Beside it (same JSON line):
+  * batched form: 64 seeded uneven images (480..4096 x 320..2160, half gray,
+    half RGB, K = 8, sigma_r ~ U[0.05, 0.3]) as one call per batch, against the
+    same images filtered one call each; eager, autotuned, and replayed from a
+    captured HIP graph;
+  * serving form: an open-loop Poisson request stream (RGB 720p/1080p/4K/8K,
+    K in {4, 8, 16}, sigma_r ~ U[0.05, 0.3], float16 pyramid storage) through
+    the continuous-batching server, latency from arrival (input in pinned host
+    memory) to output ready, upload included; p50/p99 and served MPix/s.
+
 Prints ONE JSON line on stdout.  Progress goes to stderr.
 """
 import argparse
@@ -67,6 +77,35 @@ def time_steps(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+def step_percentiles(torch, fn, steps):
+    """Per-step device time (hipEvents around each step): median and p90 in ms."""
+    import numpy as np
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in evs])
+    return float(np.median(t)), float(np.percentile(t, 90))
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of nbytes (torch's copy kernel): GB/s of read + write."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del a, b
+    return 2.0 * nbytes / dt / 1e9
+
+
 def kernel_profile(torch, ctx, fn, steps):
     ctx.timing(True)
     for _ in range(steps):
@@ -91,10 +130,150 @@ def run_form(torch, fllf, storage, x, w, steps, warmup):
         ctx.run_jobs([fj], workspace=ws, stream=stream)
 
     ms = time_steps(torch, step, steps, warmup)
-    log(f"{storage}: {ms:.4f} ms/step")
+    p50, p90 = step_percentiles(torch, step, steps)
+    log(f"{storage}: {ms:.4f} ms/step (per-step p50 {p50:.4f}, p90 {p90:.4f})")
     prof = kernel_profile(torch, ctx, step, steps)
     per_step_bytes = sum(r["bytes"] for r in prof) / steps
-    return dict(ms=ms, kernels=prof, alg_bytes_per_step=per_step_bytes, ctx=ctx, out=out)
+    return dict(ms=ms, p50=p50, p90=p90, kernels=prof, alg_bytes_per_step=per_step_bytes, ctx=ctx, out=out)
+
+
+def run_batched(torch, fllf, storages, steps, warmup):
+    """The 64-image uneven batch: one call per image vs one call per batch."""
+    from paper_2206_04681_amd.synth import batch_workloads
+    ws = batch_workloads()
+    log(f"generating the {len(ws)}-image uneven batch")
+    xs = [torch.from_numpy(w.image()).cuda() for w in ws]
+    mpix = sum(w.megapixels for w in ws)
+    res = {"images": len(ws), "mpix": round(mpix, 3),
+           "gray": sum(1 for w in ws if w.channels == 1), "rgb": sum(1 for w in ws if w.channels == 3),
+           "K": ws[0].K, "levels": sorted({w.levels for w in ws})}
+    for storage in storages:
+        ctx = fllf.FourierLLF(storage)
+        prepared = [ctx._prepare(fllf.Job(x, w.levels, w.sigma_r, w.m, w.K)) for x, w in zip(xs, ws)]
+        fjobs = [p[0] for p in prepared]
+        one = max(ctx.workspace_size([fj]) for fj in fjobs)
+        ws1 = torch.empty(one, dtype=torch.uint8, device="cuda")
+        wsb = torch.empty(ctx.workspace_size(fjobs), dtype=torch.uint8, device="cuda")
+
+        def per_image():
+            for fj in fjobs:
+                ctx.run_jobs([fj], workspace=ws1)
+
+        def batched():
+            ctx.run_jobs(fjobs, workspace=wsb)
+
+        n = max(2, steps // 4)
+        t_loop = time_steps(torch, per_image, n, 1)
+        t_batch = time_steps(torch, batched, n, 1)
+        chosen = ctx.autotune(fjobs, workspace=wsb, reps=2)
+        t_tuned = time_steps(torch, batched, n, 1)
+        g = ctx.graph(fjobs, workspace=wsb)
+        t_graph = time_steps(torch, g.launch, n, 1)
+        g.close()
+        best = min(t_batch, t_tuned, t_graph)
+        log(f"batched {storage}: per-image {t_loop:.3f} ms, batched {t_batch:.3f} ms, "
+            f"autotuned {t_tuned:.3f} ms, graph {t_graph:.3f} ms (tuning {chosen})")
+        res[storage] = {"value": round(mpix / (best * 1e-3), 2), "unit": "MPix/s",
+                        "ms_per_batch": round(best, 4),
+                        "ms_per_image_loop": round(t_loop, 4), "ms_batched": round(t_batch, 4),
+                        "ms_autotuned": round(t_tuned, 4), "ms_graph": round(t_graph, 4),
+                        "speedup_vs_per_image": round(t_loop / best, 3), "tuning": chosen,
+                        "workspace_gb": round(wsb.numel() / 1e9, 3)}
+        del wsb, ws1, prepared
+        ctx.close()
+    return res
+
+
+def serve_once(torch, fllf, reqs, hosts, storage, arena_bytes, max_active=64):
+    """Drive the server over an open-loop request list; returns latency stats."""
+    import numpy as np
+    llf = fllf.FourierLLF(storage)
+    srv = fllf.Server(llf, arena_bytes, max_active=max_active)
+    copy, comp = torch.cuda.Stream(), torch.cuda.Stream()
+    n = len(reqs)
+    lat, h2d = np.zeros(n), np.zeros(n)
+    live, done_mpix, max_queued = {}, 0.0, 0
+    i = completed = 0
+    first_done = last_done = None
+    t0 = time.perf_counter()
+    while completed < n:
+        now = time.perf_counter() - t0
+        while i < n and reqs[i].arrival <= now:
+            r = reqs[i]
+            w = r.work
+            x = torch.empty((3, w.height, w.width), dtype=torch.float32, device="cuda")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(copy):
+                e0.record(copy)
+                x.copy_(hosts[(w.height, w.width)], non_blocking=True)
+                e1.record(copy)
+            out = srv.submit(fllf.Job(x, w.levels, w.sigma_r, w.m, w.K), tag=i, ready_event=e1)
+            live[i] = (x, out, e0, e1)
+            i += 1
+        srv.step(comp)
+        max_queued = max(max_queued, srv.stats()["queued"])
+        for t in srv.poll():
+            tn = time.perf_counter() - t0
+            lat[t] = tn - reqs[t].arrival
+            x, out, e0, e1 = live.pop(t)
+            h2d[t] = e0.elapsed_time(e1) * 1e-3
+            done_mpix += reqs[t].work.megapixels
+            completed += 1
+            first_done = tn if first_done is None else first_done
+            last_done = tn
+        if not live and i < n:
+            wait = reqs[i].arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.002))
+    torch.cuda.synchronize()
+    st = srv.stats()
+    srv.close()
+    llf.close()
+    span = last_done - reqs[0].arrival
+    ms = lambda v: round(float(v) * 1e3, 3)
+    return {"requests": n, "offered_per_s": round(n / reqs[-1].arrival, 1),
+            "latency_ms_p50": ms(np.percentile(lat, 50)), "latency_ms_p99": ms(np.percentile(lat, 99)),
+            "latency_ms_mean": ms(lat.mean()), "latency_ms_max": ms(lat.max()),
+            "h2d_ms_p50": ms(np.percentile(h2d, 50)), "h2d_ms_mean": ms(h2d.mean()),
+            "h2d_share_of_latency": round(float(h2d.sum() / lat.sum()), 3),
+            "served_mpix_per_s": round(done_mpix / span, 2),
+            "arena_gb": round(st["arena_bytes"] / 1e9, 3), "arena_peak_gb": round(st["arena_peak"] / 1e9, 3),
+            "max_queued": max_queued, "steps": st["steps"], "launches": st["launches"]}
+
+
+def run_serve(torch, fllf, args):
+    from paper_2206_04681_amd.synth import serve_requests
+    reqs = serve_requests(rate=args.serve_rate, seconds=args.serve_seconds, content_variants=1)
+    log(f"serving: {len(reqs)} requests over {args.serve_seconds} s; generating one image per size")
+    hosts = {}
+    for r in reqs:
+        key = (r.work.height, r.work.width)
+        if key not in hosts:
+            hosts[key] = torch.from_numpy(r.work.image()).pin_memory()
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(args.serve_budget_gb * 1e9) if args.serve_budget_gb > 0 else int(0.5 * free)
+    res = {"storage": "f16", "rate_per_s": args.serve_rate, "seconds": args.serve_seconds}
+    res.update(serve_once(torch, fllf, reqs, hosts, "f16", budget))
+    log(f"serve: p50 {res['latency_ms_p50']} ms, p99 {res['latency_ms_p99']} ms, "
+        f"{res['served_mpix_per_s']} MPix/s")
+    if args.serve_small_budget_gb > 0:
+        short = [r for r in reqs if r.arrival < args.serve_small_seconds]
+        small = serve_once(torch, fllf, short, hosts, "f16", int(args.serve_small_budget_gb * 1e9))
+        small["seconds"] = args.serve_small_seconds
+        res["small_budget"] = small
+        log(f"serve (arena {args.serve_small_budget_gb} GB): p50 {small['latency_ms_p50']} ms, "
+            f"p99 {small['latency_ms_p99']} ms, max queued {small['max_queued']}")
+    if args.serve_sweep:
+        sweep = []
+        for rate in [float(v) for v in args.serve_sweep.split(",")]:
+            rq = serve_requests(rate=rate, seconds=args.serve_sweep_seconds, content_variants=1)
+            r = serve_once(torch, fllf, rq, hosts, "f16", budget)
+            r["rate_per_s"] = rate
+            sweep.append({k: r[k] for k in ("rate_per_s", "requests", "latency_ms_p50", "latency_ms_p99",
+                                            "served_mpix_per_s", "max_queued")})
+            log(f"saturation sweep {rate}/s: p50 {r['latency_ms_p50']} ms, p99 {r['latency_ms_p99']} ms")
+        res["saturation_sweep"] = sweep
+    return res
 
 
 def cpu_baseline(w):
@@ -126,6 +305,17 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy a buffer of this many bytes 3 times (counter calibration)")
     ap.add_argument("--digest", action="store_true", help="print the kernel source digest and exit")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving form")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="requests per second")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the request stream")
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="arena for the server (0: half of the free device memory)")
+    ap.add_argument("--serve-small-budget-gb", type=float, default=8.0,
+                    help="also serve the first --serve-small-seconds of the stream with this arena (0: skip)")
+    ap.add_argument("--serve-small-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-sweep", default="", help="comma-separated request rates for a saturation sweep")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=3.0)
     args = ap.parse_args()
     if args.digest:
         print(kernel_source_digest())
@@ -158,6 +348,7 @@ def main():
 
     main_key = args.forms.split(",")[0]  # f32 unless a run selects other forms
     main_form = forms[main_key]
+    copy_gbs = copy_bandwidth(torch)
     ms = main_form["ms"]
     mpix = w.height * w.width / 1e6
     dom = main_form["kernels"][0]
@@ -184,7 +375,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom["name"]), "avg_launch_us": round(dom_avg_s * 1e6, 2),
                      "alg_bytes_per_launch": int(dom_bytes)},
+        "ms_p50": round(main_form["p50"], 5),
+        "ms_p90": round(main_form["p90"], 5),
         "step_alg_gbs": round(main_form["alg_bytes_per_step"] / (ms * 1e-3) / 1e9, 1),
+        "copy_gbs_measured": round(copy_gbs, 1),
         "kernels": {k: [dict(name=r["name"], launches=r["launches"] // args.steps,
                              avg_us=round(r["avg_us"], 2), gbs=round(r["gbs"], 1))
                         for r in f["kernels"]] for k, f in forms.items()},
@@ -194,6 +388,10 @@ def main():
             result[f"{k}_store"] = {"value": round(mpix / (f["ms"] * 1e-3), 2), "unit": "MPix/s",
                                     "ms_per_step": round(f["ms"], 5),
                                     "speedup_vs_f32": round(ms / f["ms"], 3)}
+    if not args.no_batch:
+        result["batched"] = run_batched(torch, fllf, ["f32", "f16"], args.steps, args.warmup)
+    if not args.no_serve:
+        result["serve"] = run_serve(torch, fllf, args)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(w)
