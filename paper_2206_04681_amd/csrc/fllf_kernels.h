@@ -181,6 +181,51 @@ __device__ inline void st_records_staged(char *row, int lane, int nw, const uint
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// Coalesced record rows.  On interior strips the records a wave needs from one
+// row are one contiguous span: lane t owns records PER t .. PER t + PER - 1
+// (D = NR PER dwords).  Loading lane t's own records makes every load
+// instruction touch 64 cache lines; instead lane t loads 16-byte chunks
+// t, t + 64, ... of the span (1 KB per instruction) and the wave transposes
+// them through LDS.  In LDS each lane's D dwords are followed by 4 pad dwords,
+// which keeps both the chunk writes and the ds_read_b128 read-back free of
+// bank conflicts for every record size.
+template <int D>
+constexpr int span_slice_dwords() { return 64 * (D + 4); }
+
+template <int D>
+__device__ inline void ld_span(const Plane &p, uint32_t soff, int lane, uint32_t *q) {
+  static_assert(D % 4 == 0, "whole 16-byte chunks");
+  const uint32_t v = opaque(16u * (uint32_t)lane);
+#pragma unroll
+  for (int c = 0; c < D / 4; ++c) {
+    const uint32_t so = soff + 1024u * (uint32_t)c;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) q[4 * c + e] = p.ldu(v + 4u * e, so);
+  }
+}
+
+template <int D>
+__device__ inline void transpose_span(uint32_t *q, uint32_t *slice, int lane) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  constexpr int LD = D + 4;  // LDS dwords per lane
+#pragma unroll
+  for (int c = 0; c < D / 4; ++c) {
+    const int w = 4 * (64 * c + lane);  // dword of the span this chunk starts at
+    const int u = w / D, off = w - u * D;
+    *reinterpret_cast<u4 *>(slice + u * LD + off) = u4{q[4 * c], q[4 * c + 1], q[4 * c + 2], q[4 * c + 3]};
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+  for (int c = 0; c < D / 4; ++c) {
+    const u4 v = *reinterpret_cast<const u4 *>(slice + lane * LD + 4 * c);
+    q[4 * c] = v.x;
+    q[4 * c + 1] = v.y;
+    q[4 * c + 2] = v.z;
+    q[4 * c + 3] = v.w;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 // --------------------------------------------------------------------------
 // Index helpers
 // --------------------------------------------------------------------------
@@ -266,6 +311,13 @@ __device__ inline void vstep(float h, float &P0, float &P1, float &out) {
 // Minimum waves per SIMD a kernel is compiled for: 2 (<= 256 VGPRs) up to 8
 // terms; with 16 or 32 terms the pyramid rows need the whole register file.
 constexpr int min_waves_per_simd(int KM) { return KM <= 8 ? 2 : 1; }
+
+// The passes that read a level of records hold two fine records per lane in
+// flight; with 16-dword records (float32 K = 8) a 512-register budget at one
+// wave per SIMD beats spilling at two (measured: down_l1 167 -> 146 us).
+constexpr int down_min_waves(int KM, int DW, bool L0) {
+  return (!L0 && KM * DW >= 16) ? 1 : min_waves_per_simd(KM);
+}
 
 // --------------------------------------------------------------------------
 // Kernel arguments
@@ -354,16 +406,20 @@ struct DownWave {
   static constexpr int NR = KM * DW;  // dwords of a full record
   struct RowIn {  // one fine row as loaded (raw), for the one-row-ahead prefetch
     float g0, g1, m0, m1;
-    uint32_t q0[NR], q1[NR];
+    uint32_t q[2 * NR];  // records of fine columns x0 and x0 + 1
   };
-  // With exact K the coarse records are written through LDS (whole lines per store).
+  // With exact K the coarse records are written through LDS (whole lines per
+  // store), and on interior strips the fine records are read as coalesced spans.
   static constexpr bool STAGED = EX;
+  static constexpr bool SPAN = EX && !L0 && NR <= 16;
+  static constexpr int SLICE = !EX ? 1 : SPAN ? span_slice_dwords<2 * NR>() : staged_slice_dwords<NR>();
   const DownArgs &a;
   int c, K, nr, j, i0, i1, x0, lane, nw;
   bool writer, border;
   uint32_t rec;                                        // bytes per pair record
   uint32_t vx, vf0, vf1, vpx, vpf0, vpf1, vcj, vpcj;  // lane byte offsets
   uint32_t vrun;                                       // record offset of lane 1's coarse column
+  uint32_t vspan;                                      // record offset of lane 0's fine column x0
   uint32_t *slice;                                     // this wave's LDS staging slice
   const float *gf;
   const uint32_t *csf;
@@ -386,6 +442,7 @@ struct DownWave {
     vrun = (uint32_t)(strip * 62) * rec;
     border = sgpr(border_strip(strip, a.g.Wf));  // uniform
     x0 = 2 * j;
+    vspan = border ? 0u : (uint32_t)(2 * (strip * 62 - 1)) * rec;
     const int f0 = reflect(x0, a.g.Wf), f1 = reflect(x0 + 1, a.g.Wf);
     vx = (uint32_t)max(x0, 0) * 4u;
     vf0 = (uint32_t)f0 * 4u;
@@ -422,14 +479,22 @@ struct DownWave {
       const Plane p(csf);
       const uint32_t so = fr * (uint32_t)a.g.pf * rec;
       if (BORDER) {
-        ld_record<NR, EX>(p, opaque(vpf0), so, nr, d.q0);
-        ld_record<NR, EX>(p, opaque(vpf1), so, nr, d.q1);
+        ld_record<NR, EX>(p, opaque(vpf0), so, nr, d.q);
+        ld_record<NR, EX>(p, opaque(vpf1), so, nr, d.q + NR);
+      } else if (SPAN) {
+        ld_span<2 * NR>(p, so + vspan, lane, d.q);  // transposed before use
       } else {
         const uint32_t vo = opaque(vpx);
-        ld_record<NR, EX>(p, vo, so, nr, d.q0);
-        ld_record<NR, EX>(p, vo + rec, so, nr, d.q1);
+        ld_record<NR, EX>(p, vo, so, nr, d.q);
+        ld_record<NR, EX>(p, vo + rec, so, nr, d.q + NR);
       }
     }
+  }
+
+  // Interior strips: the loaded span chunks become this lane's two records.
+  template <bool BORDER>
+  __device__ inline void ready(RowIn &d) {
+    if (SPAN && !BORDER) transpose_span<2 * NR>(d.q, slice, lane);
   }
 
   // Consume fine row r (stream role ROLE); ROLE 4 emits coarse row ci.
@@ -461,7 +526,7 @@ struct DownWave {
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
-          const float2 q0 = PS::cvt(&d.q0[k * DW]), q1 = PS::cvt(&d.q1[k * DW]);
+          const float2 q0 = PS::cvt(&d.q[k * DW]), q1 = PS::cvt(&d.q[NR + k * DW]);
           vstep<ROLE>(hred(q0.x, q1.x), PC0[k], PC1[k], oc[k]);
           vstep<ROLE>(hred(q0.y, q1.y), PS0[k], PS1[k], os[k]);
           // level-l half of Eq. (14) (pairs carry at_k)
@@ -518,11 +583,14 @@ struct DownWave {
     RowIn A, B;
     load<BORDER>(A, 2 * i0 - 2);
     load<BORDER>(B, 2 * i0 - 1);
+    ready<BORDER>(A);
     process<0>(A, 2 * i0 - 2, i0 - 1);
     for (int i = i0 - 1; i < i1; ++i) {
       load<BORDER>(A, 2 * i + 2);
+      ready<BORDER>(B);
       process<3>(B, 2 * i + 1, i);
       load<BORDER>(B, 2 * i + 3);
+      ready<BORDER>(A);
       process<4>(A, 2 * i + 2, i);
     }
   }
@@ -534,10 +602,10 @@ struct DownWave {
 };
 
 template <int ST, int KM, bool EX, bool L0, bool MAP>
-__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownArgs a) {
+__global__ void __launch_bounds__(256, down_min_waves(KM, PairStore<ST>::DW, L0)) down_kernel(DownArgs a) {
   using W = DownWave<ST, KM, EX, L0, MAP>;
-  constexpr int SLICE = W::STAGED ? staged_slice_dwords<W::NR>() : 1;
-  __shared__ uint32_t stage[4 * SLICE];
+  constexpr int SLICE = W::SLICE;
+  __shared__ __attribute__((aligned(16))) uint32_t stage[4 * SLICE];
   int lane, strip, seg, c;
   if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
   W w(a, lane, c, strip, seg, stage + (threadIdx.x >> 6) * SLICE);
@@ -545,12 +613,12 @@ __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownA
 }
 
 template <int ST, int KM, bool EX, bool L0, bool MAP>
-__global__ void __launch_bounds__(256, min_waves_per_simd(KM))
+__global__ void __launch_bounds__(256, down_min_waves(KM, PairStore<ST>::DW, L0))
 down_batch_kernel(const DownArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n,
                   uint32_t total) {
   using W = DownWave<ST, KM, EX, L0, MAP>;
-  constexpr int SLICE = W::STAGED ? staged_slice_dwords<W::NR>() : 1;
-  __shared__ uint32_t stage[4 * SLICE];
+  constexpr int SLICE = W::SLICE;
+  __shared__ __attribute__((aligned(16))) uint32_t stage[4 * SLICE];
   const int lane = threadIdx.x & 63;
   const uint32_t stride = gridDim.x * 4u;
   for (uint32_t w = first_wave(); w < total; w += stride) {
@@ -591,16 +659,23 @@ struct UpWave {
   struct FBlk {  // fine 2x2 block as loaded: G (or I), A (or I), boost
     float g[4], b[4], m[4];
   };
+  // interior strips read each coarse row of records as one coalesced span
+  static constexpr bool SPAN = EX;
+  static constexpr int SLICE = SPAN ? span_slice_dwords<NR>() : 1;
   const UpArgs &a;
-  int c, K, nr, j, i0, i1, x0;
+  int c, K, nr, j, i0, i1, x0, lane;
   bool writer, two, border, vec_f;
   uint32_t rec, vcj, vpcj, vx, vxa, vxb;  // record bytes, lane byte offsets
+  uint32_t vspan;                         // record offset of lane 0's coarse column
+  uint32_t *slice;                        // this wave's LDS slice
   const float *gc, *oc, *base, *gfp;
   const uint32_t *csc;
   float *outp;
 
-  __device__ UpWave(const UpArgs &args, int lane, int c_, int strip, int seg) : a(args) {
+  __device__ UpWave(const UpArgs &args, int lane_, int c_, int strip, int seg, uint32_t *slice_) : a(args) {
     const Geom &g = a.g;
+    lane = lane_;
+    slice = slice_;
     c = c_;
     K = EX ? KM : a.cf.K;
     nr = K * DW;
@@ -613,6 +688,7 @@ struct UpWave {
     i1 = min(i0 + g.S, g.Hc);
     writer = lane >= 1 && lane <= 62 && j < g.Wc;
     border = sgpr(border_strip(strip, g.Wf));  // uniform
+    vspan = border ? 0u : (uint32_t)(strip * 62 - 1) * rec;
     x0 = 2 * j;
     two = x0 + 1 < g.Wf;
     // border waves read clamped columns (values of non-writer lanes are unused)
@@ -629,13 +705,20 @@ struct UpWave {
     base = a.base + (size_t)c * a.base_cs;
   }
 
+  template <bool BORDER>
   __device__ inline void load_c(CRow &d, int i) const {
     const uint32_t ci = (uint32_t)cfold(i, a.g.Hc, a.g.Hf) * (uint32_t)a.g.pc;
     if (HASD) {
       d.o = Plane(oc).ld1(vcj, ci * 4u);
       d.g = Plane(gc).ld1(vcj, ci * 4u);
     }
-    ld_record<NR, EX>(Plane(csc), opaque(vpcj), ci * rec, nr, d.q);
+    if (SPAN && !BORDER) ld_span<NR>(Plane(csc), ci * rec + vspan, lane, d.q);  // transposed before use
+    else ld_record<NR, EX>(Plane(csc), opaque(vpcj), ci * rec, nr, d.q);
+  }
+
+  template <bool BORDER>
+  __device__ inline void ready(CRow &d) {
+    if (SPAN && !BORDER) transpose_span<NR>(d.q, slice, lane);
   }
 
   // Two fine samples of one float row: clamped columns in border strips, one
@@ -679,22 +762,25 @@ struct UpWave {
     FBlk fa, fb;
     {
       CRow t;
-      load_c(t, i0 - 1);
+      load_c<BORDER>(t, i0 - 1);
+      ready<BORDER>(t);
       if (HASD) Dm = t.o - t.g;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
         if (EX || k < K) { const float2 v = PS::cvt(&t.q[k * DW]); Cm[k] = v.x; Sm[k] = v.y; }
-      load_c(t, i0);
+      load_c<BORDER>(t, i0);
+      ready<BORDER>(t);
       if (HASD) D0 = t.o - t.g;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
         if (EX || k < K) { const float2 v = PS::cvt(&t.q[k * DW]); C0[k] = v.x; S0[k] = v.y; }
     }
-    load_c(rp, i0 + 1);
+    load_c<BORDER>(rp, i0 + 1);
     load_f<BORDER>(fa, i0);
     const Plane op(outp);
     for (int i = i0; i < i1; ++i) {
-      load_c(rn, i + 2);
+      load_c<BORDER>(rn, i + 2);
+      ready<BORDER>(rp);
       load_f<BORDER>(fb, i + 1 < i1 ? i + 1 : i);
       const float Dp = HASD ? rp.o - rp.g : 0.f;
       float ED[4] = {0.f, 0.f, 0.f, 0.f};
@@ -761,15 +847,19 @@ struct UpWave {
 
 template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs a) {
+  using W = UpWave<ST, KM, EX, L0, MAP, HASD>;
+  __shared__ __attribute__((aligned(16))) uint32_t stage[4 * W::SLICE];
   int lane, strip, seg, c;
   if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
-  UpWave<ST, KM, EX, L0, MAP, HASD> w(a, lane, c, strip, seg);
+  W w(a, lane, c, strip, seg, stage + (threadIdx.x >> 6) * W::SLICE);
   w.run();
 }
 
 template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM))
 up_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n, uint32_t total) {
+  using W = UpWave<ST, KM, EX, L0, MAP, HASD>;
+  __shared__ __attribute__((aligned(16))) uint32_t stage[4 * W::SLICE];
   const int lane = threadIdx.x & 63;
   const uint32_t stride = gridDim.x * 4u;
   for (uint32_t w = first_wave(); w < total; w += stride) {
@@ -777,7 +867,7 @@ up_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restrict__ st
     const UpArgs &a = jobs[j];
     int strip, seg, c;
     job_coords(a.g, w - start[j], strip, seg, c);
-    UpWave<ST, KM, EX, L0, MAP, HASD> wv(a, lane, c, strip, seg);
+    W wv(a, lane, c, strip, seg, stage + (threadIdx.x >> 6) * W::SLICE);
     wv.run();
   }
 }
