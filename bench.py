@@ -137,6 +137,20 @@ def run_form(torch, fllf, storage, x, w, steps, warmup):
     return dict(ms=ms, p50=p50, p90=p90, kernels=prof, alg_bytes_per_step=per_step_bytes, ctx=ctx, out=out)
 
 
+def run_reparam(torch, fllf, x, w, steps, warmup, full_ms):
+    """New boost and range scale (same T) from the pyramids a run left resident."""
+    ctx = fllf.FourierLLF("f32")
+    prev, _ = ctx._prepare(fllf.Job(x, w.levels, w.sigma_r, w.m, w.K))
+    ws = torch.empty(ctx.workspace_size([prev]), dtype=torch.uint8, device="cuda")
+    ctx.run_jobs([prev], workspace=ws)
+    sigma2, m2 = 1.5 * w.sigma_r, w.m - 1.0
+    nxt, _ = ctx._prepare(fllf.Job(x, w.levels, sigma2, m2, w.K))
+    ms = time_steps(torch, lambda: ctx.reparam(prev, nxt, ws), steps, warmup)
+    log(f"reparam f32: {ms:.4f} ms (sigma_r {w.sigma_r} -> {sigma2}, m {w.m} -> {m2})")
+    return {"ms": round(ms, 5), "speedup_vs_full_run": round(full_ms / ms, 3), "sigma_r": [w.sigma_r, sigma2],
+            "m": [w.m, m2], "storage": "f32"}
+
+
 def run_batched(torch, fllf, storages, steps, warmup):
     """The 64-image uneven batch: one call per image vs one call per batch."""
     from paper_2206_04681_amd.synth import batch_workloads
@@ -388,6 +402,7 @@ def main():
             result[f"{k}_store"] = {"value": round(mpix / (f["ms"] * 1e-3), 2), "unit": "MPix/s",
                                     "ms_per_step": round(f["ms"], 5),
                                     "speedup_vs_f32": round(ms / f["ms"], 3)}
+    result["reparam"] = run_reparam(torch, fllf, x, w, args.steps, args.warmup, ms)
     if not args.no_batch:
         result["batched"] = run_batched(torch, fllf, ["f32", "f16"], args.steps, args.warmup)
     if not args.no_serve:

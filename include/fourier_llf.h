@@ -103,6 +103,26 @@ fllf_status fourier_llf_workspace_size(const fllf_ctx *ctx, const fllf_job *jobs
 fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
                             size_t ws_bytes, void *hip_stream);
 
+/* ---- re-parameterisation from resident pyramids --------------------------- */
+
+/* After fourier_llf_run(ctx, prev, 1, workspace, ...) the workspace holds the
+ * Gaussian pyramid of the input and the 2K Fourier pyramids of prev.  With the
+ * period T kept (Sec. III: the pyramids depend on the remap only through
+ * omega_k = 2 pi k / T), a new boost m or range scale sigma_r changes only the
+ * coefficients of the per-level product-sum (Eq. (11), (14)).  This call
+ * filters `next` -- the same input, size, channels, levels, K and R as prev,
+ * new m and/or sigma_r, period_T = 0 (keep prev's T) or equal to it, any
+ * output buffer -- from the resident pyramids: the product-sum and collapse
+ * passes only, each term reweighted by alpha~_k(next) / alpha~_k(prev).
+ * Exact up to float32 rounding (the weights multiply stored values); K must
+ * be 4, 8 or 16 and neither job may have a boost map (FLLF_EUNSUPPORTED
+ * otherwise, also when a term the new parameters need underflowed to zero in
+ * the resident pyramids).  The workspace must be the one prev ran in, unused
+ * since; its pyramids stay valid, so further calls may follow.  Asynchronous
+ * on hip_stream. */
+fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_job *next, void *workspace,
+                                size_t ws_bytes, void *hip_stream);
+
 /* ---- launch shape: tuning and autotuning --------------------------------- */
 
 /* Launch-shape parameters of a context (index: meaning):

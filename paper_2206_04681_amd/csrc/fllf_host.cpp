@@ -219,7 +219,10 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
   p->coefs.m = (float)job.m;
   p->coefs.K = job.K;
   p->coefs.has_map = job.m_map ? 1 : 0;
-  for (int k = 0; k < kMaxK; ++k) p->coefs.at[k] = k < job.K ? (float)at[k] : 0.0f;
+  for (int k = 0; k < kMaxK; ++k) {
+    p->coefs.at[k] = k < job.K ? (float)at[k] : 0.0f;
+    p->coefs.wt[k] = 1.0f;
+  }
 }
 
 const char *const kDownNames[kMaxLevels] = {
@@ -228,6 +231,21 @@ const char *const kDownNames[kMaxLevels] = {
 const char *const kUpNames[kMaxLevels] = {"up_l0", "up_l1", "up_l2",  "up_l3",  "up_l4",  "up_l5",
                                           "up_l6", "up_l7", "up_l8",  "up_l9",  "up_l10", "up_l11",
                                           "up_l12", "up_l13", "up_l14", "up_l15"};
+
+const char *const kHalfNames[kMaxLevels] = {
+    "half_l0", "half_l1", "half_l2",  "half_l3",  "half_l4",  "half_l5",  "half_l6",  "half_l7",
+    "half_l8", "half_l9", "half_l10", "half_l11", "half_l12", "half_l13", "half_l14", "half_l15"};
+
+hipError_t launch_reparam(const JobPlan &P, fllf_storage storage, char *ws, hipStream_t st, LaunchHook *h,
+                          const Tuning &tu) {
+  if (P.levels == 1)
+    return hipMemcpyAsync(P.out, P.in, P.lv[0].n * P.C * sizeof(float), hipMemcpyDeviceToDevice, st);
+  switch (storage) {
+    case FLLF_STORE_F16: return launch_reparam_f16(P, ws, st, h, tu);
+    case FLLF_STORE_BF16: return launch_reparam_bf16(P, ws, st, h, tu);
+    default: return launch_reparam_f32(P, ws, st, h, tu);
+  }
+}
 
 hipError_t launch_job(const JobPlan &P, fllf_storage storage, char *ws, hipStream_t st, LaunchHook *h,
                       const Tuning &tu) {
@@ -549,6 +567,45 @@ fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *wo
   fllf_status st = prepare(ctx, "run", jobs, n, workspace, ws_bytes, &plans);
   if (st != FLLF_OK) return st;
   return enqueue(ctx, plans, workspace, (hipStream_t)hip_stream, ctx->tune, ctx->timer);
+}
+
+fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_job *next, void *workspace,
+                                size_t ws_bytes, void *hip_stream) {
+  if (!prev || !next) return fail(ctx, FLLF_EINVAL, "reparam: prev and next must be non-NULL");
+  std::vector<fllf::JobPlan> plans;
+  fllf_status st = prepare(ctx, "reparam", next, 1, workspace, ws_bytes, &plans);
+  if (st != FLLF_OK) return st;
+  st = validate(ctx, prev, 1, ctx->storage);
+  if (st != FLLF_OK) return st;
+  const fllf_job &a = *prev, &b = *next;
+  if (a.in != b.in || a.width != b.width || a.height != b.height || a.channels != b.channels ||
+      a.levels != b.levels || a.K != b.K || a.range_R != b.range_R)
+    return fail(ctx, FLLF_EINVAL, "reparam: input, size, channels, levels, K and R must match the resident job");
+  if (a.m_map || b.m_map) return fail(ctx, FLLF_EUNSUPPORTED, "reparam: boost maps are not supported");
+  if (b.K != 4 && b.K != 8 && b.K != 16) return fail(ctx, FLLF_EUNSUPPORTED, "reparam: K must be 4, 8 or 16");
+  const double T = a.period_T > 0.0 ? a.period_T : fllf::fit_period(a.sigma_r, a.K, a.range_R);
+  if (b.period_T != 0.0 && b.period_T != T)
+    return fail(ctx, FLLF_EINVAL, "reparam: the period T (%.17g) must stay that of the resident pyramids", T);
+  double at_prev[fllf::kMaxK], at_next[fllf::kMaxK];
+  fllf::fourier_terms(a.sigma_r, a.K, T, nullptr, at_prev);
+  fllf::fourier_terms(b.sigma_r, b.K, T, nullptr, at_next);
+  fllf::JobPlan &P = plans[0];
+  P.coefs.inv_T = (float)(1.0 / T);
+  for (int k = 0; k < b.K; ++k) {
+    const float stored = (float)at_prev[k];  // the factor the resident pyramids carry
+    if (stored == 0.0f || !std::isfinite(at_next[k] / (double)stored)) {
+      if ((float)at_next[k] != 0.0f)
+        return fail(ctx, FLLF_EUNSUPPORTED, "reparam: term %d vanished in the resident pyramids", k + 1);
+      P.coefs.wt[k] = 0.0f;
+    } else {
+      P.coefs.wt[k] = (float)(at_next[k] / (double)stored);
+    }
+    P.coefs.at[k] = (float)at_next[k];
+  }
+  hipError_t e = fllf::launch_reparam(P, ctx->storage, (char *)workspace, (hipStream_t)hip_stream, ctx->timer,
+                                      ctx->tune);
+  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "reparam: launch failed: %s", hipGetErrorString(e));
+  return FLLF_OK;
 }
 
 fllf_status fourier_llf_set_tuning(fllf_ctx *ctx, const int32_t *params) {

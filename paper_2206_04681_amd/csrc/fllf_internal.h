@@ -27,6 +27,7 @@ struct Coefs {
   int K;
   int has_map;      // 1: per-pixel boost read from the level's m plane
   float at[kMaxK];  // alpha~_1 .. alpha~_K
+  float wt[kMaxK];  // re-parameterisation: new / resident alpha~_k (1 otherwise)
 };
 
 // Geometry and workspace placement of one pyramid level of one job.
@@ -76,6 +77,7 @@ extern const char *const kDownNames[kMaxLevels];
 extern const char *const kUpNames[kMaxLevels];
 extern const char *const kBatchDownNames[kMaxLevels];
 extern const char *const kBatchUpNames[kMaxLevels];
+extern const char *const kHalfNames[kMaxLevels];  // "half_l<l>": re-parameterisation
 
 // Launch-shape parameters.  waves[i] is the number of waves a pass aims for when
 // it picks its segment length (the kinds: 0 = down(0), 1 = down(l >= 1),
@@ -94,6 +96,14 @@ hipError_t launch_job(const JobPlan &plan, fllf_storage storage, char *ws, hipSt
 hipError_t launch_job_f32(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
 hipError_t launch_job_f16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
 hipError_t launch_job_bf16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+
+// Re-parameterised filter of a job whose pyramids are resident in ws (exact
+// K = 4, 8, 16; coefs.at / coefs.wt / coefs.m hold the new parameters).
+hipError_t launch_reparam(const JobPlan &plan, fllf_storage storage, char *ws, hipStream_t stream,
+                          LaunchHook *hook, const Tuning &tune);
+hipError_t launch_reparam_f32(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+hipError_t launch_reparam_f16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
+hipError_t launch_reparam_bf16(const JobPlan &plan, char *ws, hipStream_t stream, LaunchHook *hook, const Tuning &tune);
 
 // ---------------------------------------------------------------------------
 // Batched form: every pass (down(l), then up(l)) of all jobs that reach level

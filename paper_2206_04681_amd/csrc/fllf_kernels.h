@@ -647,7 +647,9 @@ __device__ inline void expand4(float xm, float x0, float xp, float *e) {
   e[3] = vo + ro;
 }
 
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
+// RW: re-parameterisation; the resident records carry the previous alpha~_k
+// and every term is reweighted by wt[k] (new / previous alpha~_k).
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false>
 struct UpWave {
   using PS = PairStore<ST>;
   static constexpr int DW = PS::DW;
@@ -721,6 +723,13 @@ struct UpWave {
     if (SPAN && !BORDER) transpose_span<NR>(d.q, slice, lane);
   }
 
+  // pair k of a coarse record as float32 (reweighted when re-parameterising)
+  __device__ inline float2 term(const uint32_t *q, int k) const {
+    const float2 v = PS::cvt(&q[k * DW]);
+    if (!RW) return v;
+    return make_float2(v.x * a.cf.wt[k], v.y * a.cf.wt[k]);
+  }
+
   // Two fine samples of one float row: clamped columns in border strips, one
   // contiguous 8-byte access otherwise.
   template <bool BORDER>
@@ -767,13 +776,13 @@ struct UpWave {
       if (HASD) Dm = t.o - t.g;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
-        if (EX || k < K) { const float2 v = PS::cvt(&t.q[k * DW]); Cm[k] = v.x; Sm[k] = v.y; }
+        if (EX || k < K) { const float2 v = term(t.q, k); Cm[k] = v.x; Sm[k] = v.y; }
       load_c<BORDER>(t, i0);
       ready<BORDER>(t);
       if (HASD) D0 = t.o - t.g;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
-        if (EX || k < K) { const float2 v = PS::cvt(&t.q[k * DW]); C0[k] = v.x; S0[k] = v.y; }
+        if (EX || k < K) { const float2 v = term(t.q, k); C0[k] = v.x; S0[k] = v.y; }
     }
     load_c<BORDER>(rp, i0 + 1);
     load_f<BORDER>(fa, i0);
@@ -797,7 +806,7 @@ struct UpWave {
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
-          const float2 v = PS::cvt(&rp.q[k * DW]);
+          const float2 v = term(rp.q, k);
           float EC[4], ES[4];
           expand4(Cm[k], C0[k], v.x, EC);
           expand4(Sm[k], S0[k], v.y, ES);
@@ -845,9 +854,9 @@ struct UpWave {
   }
 };
 
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs a) {
-  using W = UpWave<ST, KM, EX, L0, MAP, HASD>;
+  using W = UpWave<ST, KM, EX, L0, MAP, HASD, RW>;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * W::SLICE];
   int lane, strip, seg, c;
   if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
@@ -870,6 +879,54 @@ up_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restrict__ st
     W wv(a, lane, c, strip, seg, stage + (threadIdx.x >> 6) * W::SLICE);
     wv.run();
   }
+}
+
+// --------------------------------------------------------------------------
+// Re-parameterisation: the level-l half of Eq. (14) from resident pyramids,
+//   A_l = G_l - m sum_k wt_k (sin(w_k g) C~_{l,k} - cos(w_k g) S~_{l,k}),
+// per pixel (no stencil), for a new boost m and new alpha~_k = wt_k x the
+// resident ones.  One wave per 64 pixels of a row; rows are padded to 64, so
+// a wave's records are always one in-bounds span (read coalesced).
+// --------------------------------------------------------------------------
+struct HalfArgs {
+  const float *g; size_t g_cs;        // G_l
+  const uint32_t *cs; size_t cs_cs;   // level-l records (dwords per channel)
+  float *a; size_t a_cs;              // A_l (the O_l slot)
+  int w, h, pitch, C, blocks;         // blocks = pitch / 64 per row
+  Coefs cf;
+};
+
+template <int ST, int KM>
+__global__ void __launch_bounds__(256) half_kernel(HalfArgs a) {
+  using PS = PairStore<ST>;
+  constexpr int DW = PS::DW, NR = KM * DW;
+  __shared__ __attribute__((aligned(16))) uint32_t stage[4 * span_slice_dwords<NR>()];
+  const int lane = threadIdx.x & 63;
+  const int wv = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int blk = __builtin_amdgcn_readfirstlane(wv % a.blocks);
+  const int rest = wv / a.blocks;
+  const int y = __builtin_amdgcn_readfirstlane(rest % a.h);
+  const int c = __builtin_amdgcn_readfirstlane(rest / a.h);
+  if (c >= a.C) return;  // uniform per wave
+  const uint32_t rec = 4u * NR;
+  const uint32_t px0 = (uint32_t)y * (uint32_t)a.pitch + 64u * (uint32_t)blk;
+  const int x = 64 * blk + lane;
+  const float g = Plane(a.g + (size_t)c * a.g_cs).ld1(opaque(4u * (uint32_t)lane), px0 * 4u);
+  uint32_t q[NR];
+  ld_span<NR>(Plane(a.cs + (size_t)c * a.cs_cs), px0 * rec, lane, q);
+  transpose_span<NR>(q, stage + (threadIdx.x >> 6) * span_slice_dwords<NR>(), lane);
+  float sn, cs;
+  sincos2pi(g * a.cf.inv_T, sn, cs);
+  Harmonics h;
+  h.init(cs, sn);
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    const float2 v = PS::cvt(&q[k * DW]);
+    acc = fmaf(a.cf.wt[k] * h.s, v.x, fmaf(-a.cf.wt[k] * h.c, v.y, acc));
+    h.next();
+  }
+  if (x < a.w) Plane(a.a + (size_t)c * a.a_cs).st1(fmaf(-a.cf.m, acc, g), 4u * (uint32_t)lane, px0 * 4u);
 }
 
 // --------------------------------------------------------------------------
@@ -1029,6 +1086,60 @@ hipError_t launch_storage(const JobPlan &P, char *ws, hipStream_t st, LaunchHook
   if (km == 16) FLLF_LAUNCH(16, false);
   FLLF_LAUNCH(32, false);
 #undef FLLF_LAUNCH
+}
+
+// Re-parameterised filter of a job whose pyramids are resident in ws: the
+// half pass at levels 1 .. top-1, then the reweighted collapse passes.
+template <int ST, int KM>
+hipError_t launch_reparam_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *hook, const Tuning &tu) {
+  const int L = P.levels;
+  const int dwp = PairStore<ST>::DW;
+  const dim3 blk(256, 1, 1);
+  const double pb = 4.0 * dwp * P.K;
+  for (int l = 1; l + 1 < L; ++l) {
+    const Level &lv = P.lv[l];
+    HalfArgs a{};
+    a.g = (const float *)(ws + lv.off_g);
+    a.g_cs = lv.g_cstride;
+    a.cs = (const uint32_t *)(ws + lv.off_cs);
+    a.cs_cs = lv.cs_cstride * dwp;
+    a.a = (float *)(ws + lv.off_o);
+    a.a_cs = lv.g_cstride;
+    a.w = lv.w;
+    a.h = lv.h;
+    a.pitch = lv.pitch;
+    a.C = P.C;
+    a.blocks = lv.pitch / 64;
+    a.cf = P.coefs;
+    const long waves = (long)a.blocks * lv.h * P.C;
+    if (hook) hook->before(st);
+    half_kernel<ST, KM><<<dim3((unsigned)((waves + 3) / 4)), blk, 0, st>>>(a);
+    if (hook) hook->after(st, kHalfNames[l], (double)P.C * lv.n * (8.0 + pb));
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const UpArgs a = make_up_args(P, l, ws, dwp, tu);
+    const bool hasd = a.oc != nullptr;
+    if (hook) hook->before(st);
+    if (l == 0) {
+      if (hasd) up_kernel<ST, KM, true, true, false, true, true><<<grid_for(a.g), blk, 0, st>>>(a);
+      else up_kernel<ST, KM, true, true, false, false, true><<<grid_for(a.g), blk, 0, st>>>(a);
+    } else {
+      if (hasd) up_kernel<ST, KM, true, false, false, true, true><<<grid_for(a.g), blk, 0, st>>>(a);
+      else up_kernel<ST, KM, true, false, false, false, true><<<grid_for(a.g), blk, 0, st>>>(a);
+    }
+    if (hook) hook->after(st, kUpNames[l], up_bytes(P, l, dwp));
+  }
+  return hipGetLastError();
+}
+
+template <int ST>
+hipError_t launch_reparam_storage(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
+  switch (P.K) {
+    case 4: return launch_reparam_typed<ST, 4>(P, ws, st, h, tu);
+    case 8: return launch_reparam_typed<ST, 8>(P, ws, st, h, tu);
+    case 16: return launch_reparam_typed<ST, 16>(P, ws, st, h, tu);
+    default: return hipErrorInvalidValue;  // the caller admits K = 4, 8, 16 only
+  }
 }
 
 // --------------------------------------------------------------------------

@@ -11,4 +11,8 @@ hipError_t launch_batch_bf16(const BatchSchedule &s, char *ws, hipStream_t st, L
   return launch_batch_storage<FLLF_STORE_BF16>(s, ws, st, h, tu);
 }
 
+hipError_t launch_reparam_bf16(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
+  return launch_reparam_storage<FLLF_STORE_BF16>(P, ws, st, h, tu);
+}
+
 }  // namespace fllf

@@ -11,4 +11,8 @@ hipError_t launch_batch_f32(const BatchSchedule &s, char *ws, hipStream_t st, La
   return launch_batch_storage<FLLF_STORE_F32>(s, ws, st, h, tu);
 }
 
+hipError_t launch_reparam_f32(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
+  return launch_reparam_storage<FLLF_STORE_F32>(P, ws, st, h, tu);
+}
+
 }  // namespace fllf

@@ -30,7 +30,8 @@ EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run
             "fourier_llf_set_tuning", "fourier_llf_get_tuning", "fourier_llf_autotune",
             "fourier_llf_graph_create", "fourier_llf_graph_launch", "fourier_llf_graph_destroy",
             "fourier_llf_server_create", "fourier_llf_server_submit", "fourier_llf_server_step",
-            "fourier_llf_server_poll", "fourier_llf_server_stats", "fourier_llf_server_destroy")
+            "fourier_llf_server_poll", "fourier_llf_server_stats", "fourier_llf_server_destroy",
+            "fourier_llf_reparam")
 
 # Launch-shape parameters (FLLF_TUNE_*): target waves of the four pass kinds, grid cap.
 TUNE_NAMES = ("down0", "down", "up0", "up", "grid_cap")
@@ -138,6 +139,8 @@ def lib() -> ctypes.CDLL:
         L.fourier_llf_server_stats.restype = i32
         L.fourier_llf_server_destroy.argtypes = [vp]
         L.fourier_llf_server_destroy.restype = None
+        L.fourier_llf_reparam.argtypes = [vp, jp, jp, vp, sz, vp]
+        L.fourier_llf_reparam.restype = i32
         _LIB = L
     return _LIB
 
@@ -302,6 +305,15 @@ class FourierLLF:
         _check(lib().fourier_llf_timing_read(self._ctx, buf, cap, ctypes.byref(n)), self._ctx)
         return [dict(name=buf[i].name.decode(), launches=buf[i].launches, total_ms=buf[i].total_ms,
                      bytes=buf[i].bytes) for i in range(min(n.value, cap))]
+
+    def reparam(self, prev: FllfJob, nxt: FllfJob, workspace, stream=None) -> None:
+        """Filter `nxt` (new m / sigma_r, same T) from the pyramids `prev` left in `workspace`."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().fourier_llf_reparam(self._ctx, ctypes.byref(prev), ctypes.byref(nxt), workspace.data_ptr(),
+                                         workspace.numel(), sptr), self._ctx)
 
     # -- launch shape ----------------------------------------------------------
     def set_tuning(self, params: Optional[Sequence[int]] = None) -> None:
