@@ -321,6 +321,34 @@ def naive_llf_adaptive(I: np.ndarray, levels: int,
     return collapse(LO)
 
 
+def fast_llf(I: np.ndarray, levels: int, remap: Callable[[np.ndarray, float], np.ndarray],
+             n_samples: int, R: float = 1.0) -> np.ndarray:
+    """Fast LLF, the comparator of Sec. II-C (Aubry et al.), step by step:
+    sample n intensities tau k, k = 0 .. n-1, at equal intervals tau = R / (n-1)
+    over [0, R]; build the Laplacian pyramids of the remapped images
+    R_k = r(I, tau k); at every level l < l_max and level-l pixel p write
+    g = G_l[I]_p = tau ((1-a) k + a (k+1)) with k = floor(g / tau) and take
+    L_l[O]_p = (1-a) L_l[R_k]_p + a L_l[R_{k+1}]_p; the residual level is G_lmax[I]
+    as in naive LLF; collapse (Eq. (4)).  It uses n + 1 pyramids."""
+    if n_samples < 2:
+        raise ValueError("fast LLF needs at least 2 sampled intensities")
+    I = np.asarray(I, dtype=np.float64)
+    G = gaussian_pyramid(I, levels)
+    tau = R / (n_samples - 1)
+    LR = [laplacian_pyramid(remap(I, tau * k), levels) for k in range(n_samples)]
+    LO: List[np.ndarray] = []
+    for l in range(levels - 1):
+        t = np.clip(G[l] / tau, 0.0, n_samples - 1.0)
+        k = np.minimum(np.floor(t).astype(np.int64), n_samples - 2)
+        a = t - k
+        stack = np.stack([LR[j][l] for j in range(n_samples)])
+        lo = np.take_along_axis(stack, k[None], axis=0)[0]
+        hi = np.take_along_axis(stack, (k + 1)[None], axis=0)[0]
+        LO.append((1.0 - a) * lo + a * hi)
+    LO.append(G[levels - 1])
+    return collapse(LO)
+
+
 # --------------------------------------------------------------------------- #
 # Metrics
 # --------------------------------------------------------------------------- #
