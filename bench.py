@@ -321,6 +321,7 @@ def main():
     ap.add_argument("--digest", action="store_true", help="print the kernel source digest and exit")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving form")
+    ap.add_argument("--no-reparam", action="store_true", help="skip the re-parameterisation timing")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the request stream")
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
@@ -402,7 +403,8 @@ def main():
             result[f"{k}_store"] = {"value": round(mpix / (f["ms"] * 1e-3), 2), "unit": "MPix/s",
                                     "ms_per_step": round(f["ms"], 5),
                                     "speedup_vs_f32": round(ms / f["ms"], 3)}
-    result["reparam"] = run_reparam(torch, fllf, x, w, args.steps, args.warmup, ms)
+    if not args.no_reparam:
+        result["reparam"] = run_reparam(torch, fllf, x, w, args.steps, args.warmup, ms)
     if not args.no_batch:
         result["batched"] = run_batched(torch, fllf, ["f32", "f16"], args.steps, args.warmup)
     if not args.no_serve:
