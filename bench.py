@@ -131,10 +131,15 @@ def run_form(torch, fllf, storage, x, w, steps, warmup):
 
     ms = time_steps(torch, step, steps, warmup)
     p50, p90 = step_percentiles(torch, step, steps)
-    log(f"{storage}: {ms:.4f} ms/step (per-step p50 {p50:.4f}, p90 {p90:.4f})")
+    # the same launches replayed from a captured HIP graph
+    g = ctx.graph([fj], workspace=ws)
+    ms_graph = time_steps(torch, g.launch, steps, warmup)
+    g.close()
+    log(f"{storage}: {ms:.4f} ms/step (per-step p50 {p50:.4f}, p90 {p90:.4f}; graph replay {ms_graph:.4f})")
     prof = kernel_profile(torch, ctx, step, steps)
     per_step_bytes = sum(r["bytes"] for r in prof) / steps
-    return dict(ms=ms, p50=p50, p90=p90, kernels=prof, alg_bytes_per_step=per_step_bytes, ctx=ctx, out=out)
+    return dict(ms=ms, p50=p50, p90=p90, ms_graph=ms_graph, kernels=prof, alg_bytes_per_step=per_step_bytes,
+                ctx=ctx, out=out)
 
 
 def run_reparam(torch, fllf, x, w, steps, warmup, full_ms):
@@ -392,6 +397,7 @@ def main():
                      "alg_bytes_per_launch": int(dom_bytes)},
         "ms_p50": round(main_form["p50"], 5),
         "ms_p90": round(main_form["p90"], 5),
+        "ms_graph_replay": round(main_form["ms_graph"], 5),
         "step_alg_gbs": round(main_form["alg_bytes_per_step"] / (ms * 1e-3) / 1e9, 1),
         "copy_gbs_measured": round(copy_gbs, 1),
         "kernels": {k: [dict(name=r["name"], launches=r["launches"] // args.steps,
@@ -401,7 +407,7 @@ def main():
     for k, f in forms.items():
         if k != main_key:
             result[f"{k}_store"] = {"value": round(mpix / (f["ms"] * 1e-3), 2), "unit": "MPix/s",
-                                    "ms_per_step": round(f["ms"], 5),
+                                    "ms_per_step": round(f["ms"], 5), "ms_graph_replay": round(f["ms_graph"], 5),
                                     "speedup_vs_f32": round(ms / f["ms"], 3)}
     if not args.no_reparam:
         result["reparam"] = run_reparam(torch, fllf, x, w, args.steps, args.warmup, ms)

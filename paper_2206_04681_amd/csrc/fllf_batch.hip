@@ -30,15 +30,22 @@ const char *const kBatchUpNames[kMaxLevels] = {
     "bup_l0", "bup_l1", "bup_l2",  "bup_l3",  "bup_l4",  "bup_l5",  "bup_l6",  "bup_l7",
     "bup_l8", "bup_l9", "bup_l10", "bup_l11", "bup_l12", "bup_l13", "bup_l14", "bup_l15"};
 
-Tuning default_tuning() {
-  // Measured on the 3840x2160 RGB K = 8 workload: the level-0 passes read
-  // little per fine row and want many short segments, the passes that read a
-  // level of (C, S) records want long ones.
+Tuning default_tuning(fllf_storage storage) {
+  // Autotuned on the 3840x2160 RGB K = 8 workload.  The level-0 passes read
+  // little per fine row and want many short segments; the float32 passes
+  // that read a level of records (one wave per SIMD) want long ones.
   Tuning t;
-  t.p[kTuneDown0] = 12288;
-  t.p[kTuneDown] = 1536;
-  t.p[kTuneUp0] = 12288;
-  t.p[kTuneUp] = 1536;
+  if (storage == FLLF_STORE_F32) {
+    t.p[kTuneDown0] = 12288;
+    t.p[kTuneDown] = 512;
+    t.p[kTuneUp0] = 24576;
+    t.p[kTuneUp] = 1536;
+  } else {
+    t.p[kTuneDown0] = 6144;
+    t.p[kTuneDown] = 1536;
+    t.p[kTuneUp0] = 12288;
+    t.p[kTuneUp] = 1536;
+  }
   t.p[kTuneGridCap] = 0;
   return t;
 }
@@ -168,7 +175,7 @@ size_t step_table_bound(int n) {
 size_t batch_table_bytes(const JobPlan *plans, int n, fllf_storage storage) {
   if (n <= 1) return 0;
   BatchSchedule s;
-  build_batch(plans, n, storage, nullptr, default_tuning(), &s);
+  build_batch(plans, n, storage, nullptr, default_tuning(storage), &s);
   return s.table_bytes;
 }
 

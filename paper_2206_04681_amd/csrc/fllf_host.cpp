@@ -71,7 +71,7 @@ struct fllf_ctx {
   fllf_storage storage;
   std::string last_error;
   EventTimer *timer = nullptr;
-  fllf::Tuning tune = fllf::default_tuning();
+  fllf::Tuning tune;
   // pinned host staging of the batch table; stage_ev marks the end of its last copy
   void *stage = nullptr;
   size_t stage_cap = 0;
@@ -388,6 +388,7 @@ fllf_status fourier_llf_create(fllf_ctx **out, int device, fllf_storage storage)
   fllf_ctx *c = new fllf_ctx();
   c->device = device;
   c->storage = storage;
+  c->tune = fllf::default_tuning(storage);
   *out = c;
   return FLLF_OK;
 }
@@ -610,7 +611,7 @@ fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_
 
 fllf_status fourier_llf_set_tuning(fllf_ctx *ctx, const int32_t *params) {
   if (!ctx) return fail(nullptr, FLLF_EINVAL, "set_tuning: ctx is NULL");
-  const fllf::Tuning d = fllf::default_tuning();
+  const fllf::Tuning d = fllf::default_tuning(ctx->storage);
   fllf::Tuning t = d;
   if (params) {
     for (int i = 0; i < fllf::kTuneGridCap; ++i) t.p[i] = params[i] > 0 ? params[i] : d.p[i];

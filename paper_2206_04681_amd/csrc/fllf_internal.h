@@ -87,7 +87,7 @@ enum { kTuneDown0 = 0, kTuneDown = 1, kTuneUp0 = 2, kTuneUp = 3, kTuneGridCap = 
 struct Tuning {
   int p[kTuneParams];
 };
-Tuning default_tuning();
+Tuning default_tuning(fllf_storage storage);
 
 // Enqueues the whole filter for one planned job on `stream`.
 hipError_t launch_job(const JobPlan &plan, fllf_storage storage, char *ws, hipStream_t stream,

@@ -770,22 +770,23 @@ struct UpWave {
     CRow rp, rn;
     FBlk fa, fb;
     {
-      CRow t;
-      load_c<BORDER>(t, i0 - 1);
-      ready<BORDER>(t);
-      if (HASD) Dm = t.o - t.g;
+      // the first three coarse rows and the first fine block are all in flight at once
+      CRow t0, t1;
+      load_c<BORDER>(t0, i0 - 1);
+      load_c<BORDER>(t1, i0);
+      load_c<BORDER>(rp, i0 + 1);
+      load_f<BORDER>(fa, i0);
+      ready<BORDER>(t0);
+      if (HASD) Dm = t0.o - t0.g;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
-        if (EX || k < K) { const float2 v = term(t.q, k); Cm[k] = v.x; Sm[k] = v.y; }
-      load_c<BORDER>(t, i0);
-      ready<BORDER>(t);
-      if (HASD) D0 = t.o - t.g;
+        if (EX || k < K) { const float2 v = term(t0.q, k); Cm[k] = v.x; Sm[k] = v.y; }
+      ready<BORDER>(t1);
+      if (HASD) D0 = t1.o - t1.g;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
-        if (EX || k < K) { const float2 v = term(t.q, k); C0[k] = v.x; S0[k] = v.y; }
+        if (EX || k < K) { const float2 v = term(t1.q, k); C0[k] = v.x; S0[k] = v.y; }
     }
-    load_c<BORDER>(rp, i0 + 1);
-    load_f<BORDER>(fa, i0);
     const Plane op(outp);
     for (int i = i0; i < i1; ++i) {
       load_c<BORDER>(rn, i + 2);
