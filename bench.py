@@ -66,7 +66,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def settle(torch, fn, ms=50.0):
+    """Untimed repetitions for at least `ms` so that the device reaches steady
+    clocks after host-side work (input generation leaves it idle for seconds)."""
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        fn()
+        torch.cuda.synchronize()
+
+
 def time_steps(torch, fn, steps, warmup):
+    settle(torch, fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()

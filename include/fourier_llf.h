@@ -207,6 +207,9 @@ typedef struct {
   int64_t steps;        /* steps that enqueued work */
   int64_t launches;     /* kernel launches and copies enqueued */
   int64_t completed;    /* jobs reported by fourier_llf_server_poll */
+  int64_t passes;       /* job passes enqueued (a pass of one job in one step) */
+  int32_t max_step_jobs;/* most jobs advanced by a single step */
+  int32_t reserved;
   uint64_t arena_bytes; /* bytes available to job workspaces */
   uint64_t arena_used;  /* bytes held by admitted jobs now */
   uint64_t arena_peak;  /* largest arena_used so far */

@@ -504,14 +504,14 @@ struct DownWave {
     float oc[KM], os[KM];
     vstep<ROLE>(hred(d.g0, d.g1), PG0, PG1, og);
     if (MAP) vstep<ROLE>(hred(d.m0, d.m1), PM0, PM1, om);
-    float s, cc;
-    sincos2pi(d.g0 * a.cf.inv_T, s, cc);
-    Harmonics h0;
-    h0.init(cc, s);
-    sincos2pi(d.g1 * a.cf.inv_T, s, cc);
-    Harmonics h1;
-    h1.init(cc, s);
     if (L0) {
+      float s, cc;
+      sincos2pi(d.g0 * a.cf.inv_T, s, cc);
+      Harmonics h0;
+      h0.init(cc, s);
+      sincos2pi(d.g1 * a.cf.inv_T, s, cc);
+      Harmonics h1;
+      h1.init(cc, s);
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
@@ -522,22 +522,39 @@ struct DownWave {
         }
       }
     } else {
-      float acc0 = 0.f, acc1 = 0.f;
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
           const float2 q0 = PS::cvt(&d.q[k * DW]), q1 = PS::cvt(&d.q[NR + k * DW]);
           vstep<ROLE>(hred(q0.x, q1.x), PC0[k], PC1[k], oc[k]);
           vstep<ROLE>(hred(q0.y, q1.y), PS0[k], PS1[k], os[k]);
-          // level-l half of Eq. (14) (pairs carry at_k)
+        }
+      }
+    }
+    // the level-l half of Eq. (14) on the fine rows [2 i0, 2 i1) this wave owns
+    // (not on the rows above it that only feed the running sums); wave-uniform
+    if (!L0 && r >= 2 * i0 && r < 2 * i1 && r < a.g.Hf) {
+      float s, cc;
+      sincos2pi(d.g0 * a.cf.inv_T, s, cc);
+      Harmonics h0;
+      h0.init(cc, s);
+      sincos2pi(d.g1 * a.cf.inv_T, s, cc);
+      Harmonics h1;
+      h1.init(cc, s);
+      float acc0 = 0.f, acc1 = 0.f;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {
+          const float2 q0 = PS::cvt(&d.q[k * DW]), q1 = PS::cvt(&d.q[NR + k * DW]);
+          // pairs carry at_k
           acc0 = fmaf(h0.s, q0.x, fmaf(-h0.c, q0.y, acc0));
           acc1 = fmaf(h1.s, q1.x, fmaf(-h1.c, q1.y, acc1));
           h0.next();
           h1.next();
         }
       }
-      // this lane owns fine columns x0, x0+1 of rows [2 i0, 2 i1)
-      if (writer && r >= 2 * i0 && r < 2 * i1 && r < a.g.Hf) {
+      // this lane owns fine columns x0, x0+1
+      if (writer) {
         const float m0 = MAP ? d.m0 : a.cf.m, m1 = MAP ? d.m1 : a.cf.m;
         const Plane ap(a.af + (size_t)c * a.af_cs);
         const uint32_t so = (uint32_t)r * (uint32_t)a.g.pf * 4u;

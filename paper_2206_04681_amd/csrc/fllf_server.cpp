@@ -116,7 +116,8 @@ struct fllf_server {
   std::deque<Step> inflight;
   std::deque<uint64_t> done;
   std::vector<hipEvent_t> events;
-  int64_t steps = 0, launches = 0, completed = 0;
+  int64_t steps = 0, launches = 0, completed = 0, passes = 0;
+  int max_step_jobs = 0;
   int finishing = 0;
 };
 
@@ -291,6 +292,8 @@ fllf_status fourier_llf_server_step(fllf_server *s, void *hip_stream, int *pendi
     s->next_slot = (slot + 1) % kSlots;
     ++s->steps;
     s->launches += (int64_t)sched.launches.size();
+    s->passes += (int64_t)items.size();
+    s->max_step_jobs = std::max(s->max_step_jobs, (int)items.size());
   }
   if (pending) *pending = (int)(s->queue.size() + s->active.size()) + s->finishing + (int)s->done.size();
   return FLLF_OK;
@@ -318,6 +321,9 @@ fllf_status fourier_llf_server_stats(const fllf_server *s, fllf_server_stats *ou
   out->steps = s->steps;
   out->launches = s->launches;
   out->completed = s->completed;
+  out->passes = s->passes;
+  out->max_step_jobs = s->max_step_jobs;
+  out->reserved = 0;
   out->arena_bytes = s->arena.capacity();
   out->arena_used = s->arena.used();
   out->arena_peak = s->arena.peak();

@@ -72,7 +72,8 @@ class FllfServerStats(ctypes.Structure):
     """Mirror of ``fllf_server_stats``."""
     _fields_ = [("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("finishing", ctypes.c_int32),
                 ("max_active", ctypes.c_int32), ("steps", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("completed", ctypes.c_int64), ("arena_bytes", ctypes.c_uint64),
+                ("completed", ctypes.c_int64), ("passes", ctypes.c_int64), ("max_step_jobs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("arena_bytes", ctypes.c_uint64),
                 ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64)]
 
 

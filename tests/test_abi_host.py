@@ -147,3 +147,11 @@ def test_product_path_does_not_import_oracle():
             if fn.endswith((".py", ".cpp", ".hip", ".h")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in txt.replace("oracle-free", ""), fn
+
+
+def test_struct_mirrors_match_the_header(F):
+    # fllf_job: 2 pointers, 6 int32, 4 doubles, 1 pointer; fllf_server_stats: 4 int32,
+    # 4 int64, 2 int32, 3 uint64; fllf_kernel_time: char[32], int32, 2 doubles
+    assert ctypes.sizeof(F.FllfJob) == 2 * 8 + 6 * 4 + 4 * 8 + 8
+    assert ctypes.sizeof(F.FllfServerStats) == 4 * 4 + 4 * 8 + 2 * 4 + 3 * 8
+    assert ctypes.sizeof(F.FllfKernelTime) == 32 + 4 + 4 + 2 * 8

@@ -73,6 +73,11 @@ def test_mix_equals_alone(torch_dev, storage):
     assert stats["completed"] == len(REQS)
     assert stats["arena_used"] == 0 and 0 < stats["arena_peak"] <= stats["arena_bytes"]
     assert stats["active"] == stats["queued"] == stats["finishing"] == 0
+    # every pass of every job was enqueued once; jobs in flight together shared
+    # steps and launches (continuous batching, not a queue)
+    assert stats["passes"] == sum(1 if L == 1 else 2 * (L - 1) for _, L, *_ in REQS)
+    assert stats["max_step_jobs"] >= 3
+    assert stats["launches"] < stats["passes"]
     for i, (x, o) in outs.items():
         _, L, s, m, K = REQS[i]
         alone = llf.run(x, L, s, m, K)
@@ -112,6 +117,7 @@ def test_max_active_one_serialises(torch_dev):
     hosts = _inputs(torch, 700)
     outs, stats, peak_queued, llf = _serve(torch, "f32", 1 << 30, hosts, max_active=1)
     assert stats["completed"] == len(REQS) and peak_queued > 0
+    assert stats["max_step_jobs"] == 1
     for i, (x, o) in outs.items():
         _, L, s, m, K = REQS[i]
         assert torch.equal(llf.run(x, L, s, m, K), o), i
