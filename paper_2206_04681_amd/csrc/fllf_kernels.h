@@ -283,8 +283,14 @@ struct Harmonics {
 
 // Unnormalised horizontal REDUCE at the lane's even fine column 2j from its
 // samples v0 (2j), v1 (2j+1) and its neighbours': taps [1 4 6 4 1].
+// Each lane shift feeds exactly one add (folded into a DPP add), and the result
+// is pinned where it is computed so that no part of the sum sinks into a
+// conditional block away from its shifts.
 __device__ inline float hred(float v0, float v1) {
-  return fmaf(6.f, v0, fmaf(4.f, from_left(v1) + v1, from_left(v0) + from_right(v0)));
+  const float t = from_right(v0) + v0;  // v_{2j} + v_{2j+2}
+  float h = fmaf(5.f, v0, fmaf(4.f, from_left(v1) + v1, from_left(v0) + t));
+  asm volatile("" : "+v"(h));
+  return h;
 }
 
 // Vertical REDUCE as running sums over a stream of horizontally reduced rows.
@@ -312,12 +318,6 @@ __device__ inline void vstep(float h, float &P0, float &P1, float &out) {
 // terms; with 16 or 32 terms the pyramid rows need the whole register file.
 constexpr int min_waves_per_simd(int KM) { return KM <= 8 ? 2 : 1; }
 
-// The passes that read a level of records hold two fine records per lane in
-// flight; with 16-dword records (float32 K = 8) a 512-register budget at one
-// wave per SIMD beats spilling at two (measured: down_l1 167 -> 146 us).
-constexpr int down_min_waves(int KM, int DW, bool L0) {
-  return (!L0 && KM * DW >= 16) ? 1 : min_waves_per_simd(KM);
-}
 
 // --------------------------------------------------------------------------
 // Kernel arguments
@@ -619,7 +619,7 @@ struct DownWave {
 };
 
 template <int ST, int KM, bool EX, bool L0, bool MAP>
-__global__ void __launch_bounds__(256, down_min_waves(KM, PairStore<ST>::DW, L0)) down_kernel(DownArgs a) {
+__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownArgs a) {
   using W = DownWave<ST, KM, EX, L0, MAP>;
   constexpr int SLICE = W::SLICE;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * SLICE];
@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(256, down_min_waves(KM, PairStore<ST>::DW, L0)
 }
 
 template <int ST, int KM, bool EX, bool L0, bool MAP>
-__global__ void __launch_bounds__(256, down_min_waves(KM, PairStore<ST>::DW, L0))
+__global__ void __launch_bounds__(256, min_waves_per_simd(KM))
 down_batch_kernel(const DownArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n,
                   uint32_t total) {
   using W = DownWave<ST, KM, EX, L0, MAP>;
@@ -654,14 +654,15 @@ down_batch_kernel(const DownArgs *__restrict__ jobs, const uint32_t *__restrict_
 // Unnormalised EXPAND of one plane onto the lane's 2x2 fine block from coarse
 // rows i-1, i, i+1 at the lane's column (xm, x0, xp) and the neighbour lanes'.
 // e[0..3] = (2i, 2j), (2i, 2j+1), (2i+1, 2j), (2i+1, 2j+1).
+// Written so that every neighbour value is used by exactly one add, which
+// the backend folds into a DPP add (no separate lane-shift moves).
 __device__ inline void expand4(float xm, float x0, float xp, float *e) {
   const float ve = fmaf(6.f, x0, xm + xp);
   const float vo = x0 + xp;
-  const float re = from_right(ve), ro = from_right(vo);
-  e[0] = fmaf(6.f, ve, from_left(ve) + re);
-  e[1] = ve + re;
-  e[2] = fmaf(6.f, vo, from_left(vo) + ro);
-  e[3] = vo + ro;
+  e[1] = from_right(ve) + ve;                  // ve_j + ve_{j+1}
+  e[0] = fmaf(5.f, ve, from_left(ve) + e[1]);  // ve_{j-1} + 6 ve_j + ve_{j+1}
+  e[3] = from_right(vo) + vo;
+  e[2] = fmaf(5.f, vo, from_left(vo) + e[3]);
 }
 
 // RW: re-parameterisation; the resident records carry the previous alpha~_k
@@ -839,16 +840,20 @@ struct UpWave {
           S0[k] = v.y;
         }
       }
-      if (writer) {
-        // EXPAND weights (1 6 1)/8 and (1 1)/2 per axis, by the block position
-        const float scl[4] = {1.f / 64.f, 1.f / 16.f, 1.f / 16.f, 1.f / 4.f};
-        float o[4];
+      // EXPAND weights (1 6 1)/8 and (1 1)/2 per axis, by the block position
+      const float scl[4] = {1.f / 64.f, 1.f / 16.f, 1.f / 16.f, 1.f / 4.f};
+      float o[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const float mp = MAP ? fa.m[p] : a.cf.m;
-          const float bp = L0 ? fa.g[p] : fa.b[p];
-          o[p] = fmaf(scl[p], fmaf(mp, acc[p], ED[p]), bp);
-        }
+      for (int p = 0; p < 4; ++p) {
+        const float mp = MAP ? fa.m[p] : a.cf.m;
+        const float bp = L0 ? fa.g[p] : fa.b[p];
+        o[p] = fmaf(scl[p], fmaf(mp, acc[p], ED[p]), bp);
+        // computed by every lane here: keeps the arithmetic next to its lane
+        // shifts, which then fold into DPP adds (else it sinks into the
+        // writers-only block below and every shift stays a separate move)
+        asm volatile("" : "+v"(o[p]));
+      }
+      if (writer) {
         const uint32_t r0 = 2 * i;
         const bool row1 = (int)r0 + 1 < g.Hf;
         const uint32_t s0 = r0 * (uint32_t)g.pf * 4u, s1 = s0 + (uint32_t)g.pf * 4u;
