@@ -250,7 +250,9 @@ void fourier_llf_server_destroy(fllf_server *srv);
 /* Aggregated device time of one kernel class over the launches recorded since
  * timing was enabled (or last read). */
 typedef struct {
-  char name[32];      /* kernel class, e.g. "down0", "down", "up0", "up" */
+  char name[32];      /* kernel class: "down_l<l>" (REDUCE from level l), "up_l<l>"
+                         (product-sum and collapse at level l), "bdown_l<l>" / "bup_l<l>"
+                         (batched launches), "half_l<l>" (re-parameterisation), "copy" */
   int32_t launches;   /* number of launches */
   double total_ms;    /* summed hipEvent durations */
   double bytes;       /* summed algorithmic HBM bytes of those launches */
