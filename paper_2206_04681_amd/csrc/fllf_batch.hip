@@ -38,10 +38,10 @@ Tuning default_tuning(fllf_storage storage) {
   if (storage == FLLF_STORE_F32) {
     t.p[kTuneDown0] = 12288;
     t.p[kTuneDown] = 512;
-    t.p[kTuneUp0] = 24576;
+    t.p[kTuneUp0] = 1536;  // as fast as 8-row segments, without re-reading a quarter of the records
     t.p[kTuneUp] = 1536;
   } else {
-    t.p[kTuneDown0] = 6144;
+    t.p[kTuneDown0] = 12288;
     t.p[kTuneDown] = 1536;
     t.p[kTuneUp0] = 12288;
     t.p[kTuneUp] = 1536;
