@@ -155,3 +155,13 @@ def test_struct_mirrors_match_the_header(F):
     assert ctypes.sizeof(F.FllfJob) == 2 * 8 + 6 * 4 + 4 * 8 + 8
     assert ctypes.sizeof(F.FllfServerStats) == 4 * 4 + 4 * 8 + 2 * 4 + 3 * 8
     assert ctypes.sizeof(F.FllfKernelTime) == 32 + 4 + 4 + 2 * 8
+
+
+def test_validate_rejects_record_planes_past_32bit_offsets(F):
+    # kernels address one channel's level-1 record plane with 32-bit byte offsets:
+    # 16384 x 16384, K = 8 needs 8192 x 8192 x 8 pairs x 8 bytes = 4 GiB in float32
+    big = dict(width=16384, height=16384, levels=2, K=8, out_ptr=0x10000000000)
+    assert F.validate([_job(F, **big)], "f32") == F.FLLF_EINVAL
+    assert "4 GiB" in F.last_error()
+    # the same image with 16-bit pairs (2 GiB) is accepted
+    assert F.validate([_job(F, **big)], "f16") == F.FLLF_OK

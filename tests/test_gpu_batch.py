@@ -184,3 +184,21 @@ def test_uneven_batch_of_64_full_size(torch_dev):
         w = ws[i]
         want = ref.fourier_llf_image(xs[i].cpu().numpy().astype(np.float64), w.levels, w.sigma_r, w.m, w.K)
         assert ref.max_abs(prepared[i][1].cpu().numpy(), want) <= TOL_F32, i
+
+
+def test_batch_with_one_invalid_job_launches_nothing(torch_dev):
+    torch = torch_dev
+    from paper_2206_04681_amd import fllf
+    ctx = _ctx()
+    jobs, fjobs, outs = _mixed_jobs(torch, ctx, specs=MIXED[:3], seed=90)
+    for o in outs:
+        o.fill_(-5.0)
+    bad = fllf.make_job(fjobs[1].in_, outs[1].data_ptr(), fjobs[1].width, fjobs[1].height, fjobs[1].channels,
+                        fjobs[1].levels, 0.1, 2.0, 40)  # K above the maximum
+    ws = torch.empty(ctx.workspace_size(fjobs), dtype=torch.uint8, device="cuda")
+    with pytest.raises(fllf.FourierLLFError) as e:
+        ctx.run_jobs([fjobs[0], bad, fjobs[2]], workspace=ws)
+    assert e.value.status == fllf.FLLF_EINVAL
+    torch.cuda.synchronize()
+    for o in outs:
+        assert bool((o == -5.0).all())
