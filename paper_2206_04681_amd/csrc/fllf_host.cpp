@@ -507,11 +507,21 @@ static fllf_status prepare(fllf_ctx *ctx, const char *who, const fllf_job *jobs,
     return fail(ctx, FLLF_ENOMEM, "%s: workspace has %zu bytes, %zu needed", who, ws_bytes, need);
   if (((uintptr_t)workspace) % fllf::kAlign != 0)
     return fail(ctx, FLLF_EINVAL, "%s: workspace must be %zu-byte aligned", who, fllf::kAlign);
+  // the workspace is written before the images are read: it must not overlap any of them
+  const char *wsb = (const char *)workspace;
+  auto hits = [&](const void *p, size_t bytes) {
+    const char *q = (const char *)p;
+    return need > 0 && q && q < wsb + need && wsb < q + bytes;
+  };
   for (int i = 0; i < n; ++i) {
-    const char *wsb = (const char *)workspace, *o = (const char *)jobs[i].out;
-    size_t ob = (size_t)jobs[i].width * jobs[i].height * jobs[i].channels * sizeof(float);
-    if (need > 0 && o < wsb + need && wsb < o + ob)
+    const size_t plane = (size_t)jobs[i].width * jobs[i].height * sizeof(float);
+    const size_t ob = plane * jobs[i].channels;
+    if (hits(jobs[i].out, ob))
       return fail(ctx, FLLF_EINVAL, "%s: job %d output overlaps the workspace", who, i);
+    if (hits(jobs[i].in, ob))
+      return fail(ctx, FLLF_EINVAL, "%s: job %d input overlaps the workspace", who, i);
+    if (hits(jobs[i].m_map, plane))
+      return fail(ctx, FLLF_EINVAL, "%s: job %d boost map overlaps the workspace", who, i);
   }
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "%s: hipSetDevice: %s", who, hipGetErrorString(e));

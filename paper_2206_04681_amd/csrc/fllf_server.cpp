@@ -201,10 +201,13 @@ fllf_status fourier_llf_server_submit(fllf_server *s, const fllf_job *job, uint6
   const fllf_storage storage = fllf::ctx_storage(ctx);
   fllf_status st = fllf::validate_jobs(ctx, job, 1, storage);
   if (st != FLLF_OK) return st;
-  const size_t ob = (size_t)job->width * job->height * job->channels * sizeof(float);
-  const char *o = (const char *)job->out;
-  if (o < s->base + s->bytes && s->base < o + ob)
-    return fllf::ctx_fail(ctx, FLLF_EINVAL, "server_submit: output overlaps the arena");
+  const size_t plane = (size_t)job->width * job->height * sizeof(float);
+  auto hits = [&](const void *p, size_t bytes) {
+    const char *q = (const char *)p;
+    return q && q < s->base + s->bytes && s->base < q + bytes;
+  };
+  if (hits(job->out, plane * job->channels) || hits(job->in, plane * job->channels) || hits(job->m_map, plane))
+    return fllf::ctx_fail(ctx, FLLF_EINVAL, "server_submit: the job's images overlap the arena");
   Job *j = new Job();
   j->job = *job;
   j->tag = tag;

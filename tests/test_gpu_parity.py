@@ -157,3 +157,22 @@ def test_small_workspace_is_rejected_before_launch(torch_dev):
     assert e.value.status == fllf.FLLF_ENOMEM
     torch.cuda.synchronize()
     assert bool((out == -7.0).all())
+
+
+def test_input_inside_the_workspace_is_rejected(torch_dev):
+    torch = torch_dev
+    from paper_2206_04681_amd import fllf
+    ctx = llf()
+    h, w = 64, 64
+    probe = fllf.make_job(0x1000, 0x100000000, w, h, 1, 4, 0.2, 2.0, 4)
+    need = ctx.workspace_size([probe])
+    ws = torch.empty(need + h * w * 4, dtype=torch.uint8, device="cuda")
+    x = ws[:h * w * 4].view(torch.float32).view(1, h, w)  # the input lives in the workspace
+    x.copy_(torch.from_numpy(_img(h, w)).cuda())
+    out = torch.full_like(x, -3.0)
+    fj, _ = ctx._prepare(fllf.Job(x, 4, 0.2, 2.0, 4, out=out))
+    with pytest.raises(fllf.FourierLLFError) as e:
+        ctx.run_jobs([fj], workspace=ws)
+    assert e.value.status == fllf.FLLF_EINVAL and "input overlaps" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool((out == -3.0).all())

@@ -146,3 +146,17 @@ def test_oversized_job_is_refused(torch_dev):
         assert torch.equal(llf.run(small, 5, 0.2, 2.0, 4), out)
     finally:
         srv.close()
+
+
+def test_images_inside_the_arena_are_refused(torch_dev):
+    torch = torch_dev
+    from paper_2206_04681_amd.fllf import FourierLLF, FourierLLFError, Job, Server, FLLF_EINVAL
+    llf = FourierLLF("f32")
+    srv = Server(llf, 64 << 20, max_active=4)
+    try:
+        x = srv.arena[-(64 * 80 * 4):].view(torch.float32).view(1, 64, 80)  # input inside the arena
+        with pytest.raises(FourierLLFError) as e:
+            srv.submit(Job(x, 5, 0.2, 2.0, 4), tag=1)
+        assert e.value.status == FLLF_EINVAL
+    finally:
+        srv.close()
