@@ -39,13 +39,14 @@ Tuning default_tuning(fllf_storage storage) {
     t.p[kTuneDown0] = 12288;
     t.p[kTuneDown] = 512;
     t.p[kTuneUp0] = 1536;  // as fast as 8-row segments, without re-reading a quarter of the records
-    t.p[kTuneUp] = 1536;
   } else {
     t.p[kTuneDown0] = 12288;
     t.p[kTuneDown] = 1536;
     t.p[kTuneUp0] = 12288;
-    t.p[kTuneUp] = 1536;
   }
+  // up(l >= 1) is the one-plane collapse on the large levels: little work per
+  // row, so short segments (many waves) hide the row latency
+  t.p[kTuneUp] = 12288;
   t.p[kTuneGridCap] = 0;
   return t;
 }
@@ -56,14 +57,13 @@ int pair_dwords(fllf_storage s) { return s == FLLF_STORE_F32 ? 2 : 1; }
 
 // Waves of pass down(l) / up(l) of one job (the same geometry the launch uses).
 uint32_t pass_waves(const JobPlan &P, int l, bool down, const Tuning &tu) {
-  const int kind = down ? (l == 0 ? kTuneDown0 : kTuneDown) : (l == 0 ? kTuneUp0 : kTuneUp);
-  const Geom g = make_geom(P.lv[l], P.lv[l + 1], P.C, pick_segment(P.lv[l + 1], P.C, tu.p[kind]));
-  return (uint32_t)geom_waves(g);
+  return (uint32_t)geom_waves(pass_geom(P, l, down, tu));
 }
 
 // Appends to the table `out->blob` (growing it) one launch per kernel class of
 // the given (job, pass) items.  Items of one class may be at different levels:
-// down(l >= 1) passes of any level share a kernel, as do up(l >= 1) passes.
+// down(l >= 1) passes of any level share a kernel, as do up(l >= 1) passes, and
+// the collapses of all fused levels share one launch.
 void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning &tu, BatchSchedule *out) {
   size_t off = out->blob.size();
   auto reserve = [&](size_t bytes) {
@@ -72,8 +72,8 @@ void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning 
     out->blob.resize(off, 0);
     return at;
   };
-  // (kind, level-0 pass, K loop, exact, map, has O_{l+1})
-  typedef std::tuple<int, bool, int, bool, bool, bool> Key;
+  // (kind, level-0 pass, K loop, exact, map, has O_{l+1}, fused level)
+  typedef std::tuple<int, bool, int, bool, bool, bool, bool> Key;
   std::map<Key, std::vector<int>> groups;
   for (int i = 0; i < n; ++i) {
     const PassItem &it = items[i];
@@ -91,7 +91,11 @@ void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning 
     bool ex;
     k_class(it.P->K, &km, &ex);
     const bool hasd = !it.down && it.l + 1 < it.P->levels - 1;
-    groups[Key(it.down ? 0 : 1, it.l == 0, km, ex, it.P->m_map != nullptr, hasd)].push_back(i);
+    const bool fuse = fused_level(*it.P, it.l);
+    if (!it.down && fuse)  // the collapse: one kernel for every job
+      groups[Key(1, false, 0, false, false, false, true)].push_back(i);
+    else
+      groups[Key(it.down ? 0 : 1, it.l == 0, km, ex, it.P->m_map != nullptr, hasd, fuse)].push_back(i);
   }
   for (auto &kv : groups) {
     const std::vector<int> &is = kv.second;
@@ -103,6 +107,7 @@ void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning 
     b.ex = std::get<3>(kv.first);
     b.map = std::get<4>(kv.first);
     b.hasd = std::get<5>(kv.first);
+    b.fuse = std::get<6>(kv.first);
     b.level = items[is[0]].l;  // the finest level of the group names the launch
     for (int i : is) b.level = std::min(b.level, items[i].l);
     b.njobs = (int)is.size();
@@ -120,7 +125,8 @@ void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning 
           const DownArgs a = make_down_args(*it.P, it.l, ws, dwp, tu);
           std::memcpy(out->blob.data() + b.args_off + rec * q, &a, rec);
         } else {
-          const UpArgs a = make_up_args(*it.P, it.l, ws, dwp, tu);
+          UpArgs a = make_up_args(*it.P, it.l, ws, dwp, tu);
+          if (b.fuse && !a.oc) a.oc = a.gc;  // the collapse expands G_{l+1} at the top
           std::memcpy(out->blob.data() + b.args_off + rec * q, &a, rec);
         }
       }
@@ -166,8 +172,9 @@ void build_batch(const JobPlan *P, int n, fllf_storage storage, char *ws, const 
 
 size_t step_table_bound(int n) {
   // per launch group: the records and n_g + 1 offsets, each padded to kAlign;
-  // at most 2 kinds x 2 level-0 flags x 6 K loops x 2 maps x 2 top flags groups
-  const size_t groups = 96;
+  // groups: down 6 K loops x 2 maps x (level 0, separate, fused) = 36, up
+  // 6 x 2 x 2 top flags x (level 0, separate) = 48, and the collapse
+  const size_t groups = 85;
   const size_t rec = std::max(sizeof(DownArgs), sizeof(UpArgs));
   return align_up(rec * (size_t)n + 4 * (size_t)n + groups * (4 + 2 * (kAlign - 1)));
 }

@@ -115,6 +115,7 @@ struct BatchLaunch {
   int kind;           // 0 = down, 1 = up, 2 = copy (single-level job: in -> out)
   int level;          // l of down(l) / up(l)
   bool l0, map, hasd; // level-0 variant, boost map, O_{l+1} present (up)
+  bool fuse;          // fused level: down finishes L_l[O]; up is the collapse
   int km;             // K loop length (4, 8, 16 or 32)
   bool ex;            // K == km exactly
   int njobs;

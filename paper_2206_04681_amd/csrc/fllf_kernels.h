@@ -156,7 +156,7 @@ __device__ inline void st_record(const Plane &p, uint32_t voff, uint32_t soff, i
 template <int NR>
 constexpr int staged_slice_dwords() { return 64 * (NR + 4); }
 
-template <int NR>
+template <int NR, int FIRST = 1>
 __device__ inline void st_records_staged(char *row, int lane, int nw, const uint32_t *d, uint32_t *slice) {
   static_assert(NR % 4 == 0, "records must be whole 16-byte pieces");
   constexpr int PIECES = NR / 4, STRIDE = NR + 4, ITER = (62 * PIECES + 63) / 64;
@@ -165,7 +165,7 @@ __device__ inline void st_records_staged(char *row, int lane, int nw, const uint
     *reinterpret_cast<uint4 *>(slice + lane * STRIDE + 4 * i) =
         make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  const int total = nw * PIECES;  // 16-byte pieces to store, record of lane 1 first
+  const int total = nw * PIECES;  // 16-byte pieces to store, record of lane FIRST first
   // an explicitly global pointer: plain global_store_dwordx4 (not flat) even
   // when the record plane's base was loaded from memory
   typedef uint32_t u4 __attribute__((ext_vector_type(4)));
@@ -174,7 +174,7 @@ __device__ inline void st_records_staged(char *row, int lane, int nw, const uint
 #pragma unroll
   for (int q = 0; q < ITER; ++q) {
     const int t = min(q * 64 + lane, total - 1);
-    const int r = t / PIECES + 1, part = t - (r - 1) * PIECES;
+    const int r = t / PIECES + FIRST, part = t - (r - FIRST) * PIECES;
     const u4 v = *reinterpret_cast<const u4 *>(slice + r * STRIDE + 4 * part);
     if (q * 64 + lane < total) dst[t] = v;
   }
@@ -293,6 +293,20 @@ __device__ inline float hred(float v0, float v1) {
   return h;
 }
 
+// Unnormalised EXPAND of one plane onto the lane's 2x2 fine block from coarse
+// rows i-1, i, i+1 at the lane's column (xm, x0, xp) and the neighbour lanes'.
+// e[0..3] = (2i, 2j), (2i, 2j+1), (2i+1, 2j), (2i+1, 2j+1).
+// Written so that every neighbour value is used by exactly one add, which
+// the backend folds into a DPP add (no separate lane-shift moves).
+__device__ inline void expand4(float xm, float x0, float xp, float *e) {
+  const float ve = fmaf(6.f, x0, xm + xp);
+  const float vo = x0 + xp;
+  e[1] = from_right(ve) + ve;                  // ve_j + ve_{j+1}
+  e[0] = fmaf(5.f, ve, from_left(ve) + e[1]);  // ve_{j-1} + 6 ve_j + ve_{j+1}
+  e[3] = from_right(vo) + vo;
+  e[2] = fmaf(5.f, vo, from_left(vo) + e[3]);
+}
+
 // Vertical REDUCE as running sums over a stream of horizontally reduced rows.
 // P0 accumulates coarse row i, P1 coarse row i+1.  Weights [1 4 6 4 1]/256
 // carry the 2-D normalisation.  Roles (row of the stream):
@@ -392,15 +406,16 @@ __device__ inline void job_coords(const Geom &g, uint32_t wv, int &strip, int &s
 
 // A wave touches columns outside [0, Wf) only in the first strip and in the
 // strips whose lane 63 (coarse column 62 s + 62) reaches fine column Wf - 1.
-__device__ inline bool border_strip(int strip, int Wf) {
-  return strip == 0 || 2 * (62 * strip + 62) + 1 >= Wf;
+__device__ inline bool border_strip(int strip, int Wf, int sw = 62, int hl = 1) {
+  return strip == 0 || 2 * (sw * strip + 63 - hl) + 1 >= Wf;
 }
 
 // --------------------------------------------------------------------------
 // down(l)
 // --------------------------------------------------------------------------
-template <int ST, int KM, bool EX, bool L0, bool MAP>
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE>
 struct DownWave {
+  static_assert(!(L0 && FUSE), "level 0 has no Laplacian to finish");
   using PS = PairStore<ST>;
   static constexpr int DW = PS::DW;
   static constexpr int NR = KM * DW;  // dwords of a full record
@@ -413,9 +428,15 @@ struct DownWave {
   static constexpr bool STAGED = EX;
   static constexpr bool SPAN = EX && !L0 && NR <= 16;
   static constexpr int SLICE = !EX ? 1 : SPAN ? span_slice_dwords<2 * NR>() : staged_slice_dwords<NR>();
+  // FUSE (levels >= 1): the pass also finishes the level-l Laplacian of the
+  // output from the fresh coarse rows: strips of 60 coarse columns with two
+  // halo lanes a side, so that the coarse values EXPAND needs (lanes 1 .. 62)
+  // are exact.  Otherwise levels >= 1 store the level-l half A_l only.
+  static constexpr int SW = FUSE ? 60 : 62;  // coarse columns per strip
+  static constexpr int HL = FUSE ? 2 : 1;    // halo lanes on each side
   const DownArgs &a;
   int c, K, nr, j, i0, i1, x0, lane, nw;
-  bool writer, border;
+  bool writer, border, two;
   uint32_t rec;                                        // bytes per pair record
   uint32_t vx, vf0, vf1, vpx, vpf0, vpf1, vcj, vpcj;  // lane byte offsets
   uint32_t vrun;                                       // record offset of lane 1's coarse column
@@ -425,6 +446,11 @@ struct DownWave {
   const uint32_t *csf;
   float PG0, PG1, PM0, PM1;
   float PC0[KM], PC1[KM], PS0[KM], PS1[KM];
+  // FUSE: coarse rows ci-2, ci-1, ci (G and the at_k-weighted pairs) ...
+  float Gm, G0, Gp, Cm[KM], C0[KM], Cp[KM], Sm[KM], S0[KM], Sp[KM];
+  // ... and, for fine rows 2ci-2 .. 2ci+1 at columns x0, x0+1: the level-l half
+  // A, cos/sin(omega_1 g) and the boost, waiting for coarse row ci
+  float pA[4][2], pc[4][2], ps[4][2], pm[4][2];
 
   __device__ DownWave(const DownArgs &args, int lane_, int c_, int strip, int seg, uint32_t *slice_)
       : a(args) {
@@ -434,15 +460,24 @@ struct DownWave {
     K = EX ? KM : a.cf.K;
     nr = K * DW;
     rec = 4u * (uint32_t)nr;
-    j = strip * 62 + lane - 1;
+    j = strip * SW + lane - HL;
     i0 = seg * a.g.S;
     i1 = min(i0 + a.g.S, a.g.Hc);
-    writer = lane >= 1 && lane <= 62 && j < a.g.Wc;
-    nw = min(62, a.g.Wc - strip * 62);  // writer lanes are 1 .. nw
-    vrun = (uint32_t)(strip * 62) * rec;
-    border = sgpr(border_strip(strip, a.g.Wf));  // uniform
+    writer = lane >= HL && lane <= 63 - HL && j < a.g.Wc;
+    nw = min(SW, a.g.Wc - strip * SW);  // writer lanes are HL .. HL + nw - 1
+    vrun = (uint32_t)(strip * SW) * rec;
+    border = sgpr(border_strip(strip, a.g.Wf, SW, HL));  // uniform
     x0 = 2 * j;
-    vspan = border ? 0u : (uint32_t)(2 * (strip * 62 - 1)) * rec;
+    two = x0 + 1 < a.g.Wf;
+    vspan = border ? 0u : (uint32_t)(2 * (strip * SW - HL)) * rec;
+    if (FUSE) {
+      Gm = G0 = Gp = 0.f;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) Cm[k] = C0[k] = Cp[k] = Sm[k] = S0[k] = Sp[k] = 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        for (int e = 0; e < 2; ++e) pA[q][e] = pc[q][e] = ps[q][e] = pm[q][e] = 0.f;
+    }
     const int f0 = reflect(x0, a.g.Wf), f1 = reflect(x0 + 1, a.g.Wf);
     vx = (uint32_t)max(x0, 0) * 4u;
     vf0 = (uint32_t)f0 * 4u;
@@ -531,16 +566,18 @@ struct DownWave {
         }
       }
     }
-    // the level-l half of Eq. (14) on the fine rows [2 i0, 2 i1) this wave owns
-    // (not on the rows above it that only feed the running sums); wave-uniform
+    // the level-l half of Eq. (14), A = G_l - m sum_k at_k (sin C~ - cos S~), on
+    // the fine rows [2 i0, 2 i1) this wave owns (not on the rows above or below
+    // that only feed the running sums); wave-uniform
+    float A0 = 0.f, A1 = 0.f, c0 = 0.f, s0 = 0.f, c1 = 0.f, s1 = 0.f;
+    const float m0 = MAP ? d.m0 : a.cf.m, m1 = MAP ? d.m1 : a.cf.m;
     if (!L0 && r >= 2 * i0 && r < 2 * i1 && r < a.g.Hf) {
-      float s, cc;
-      sincos2pi(d.g0 * a.cf.inv_T, s, cc);
+      sincos2pi(d.g0 * a.cf.inv_T, s0, c0);
       Harmonics h0;
-      h0.init(cc, s);
-      sincos2pi(d.g1 * a.cf.inv_T, s, cc);
+      h0.init(c0, s0);
+      sincos2pi(d.g1 * a.cf.inv_T, s1, c1);
       Harmonics h1;
-      h1.init(cc, s);
+      h1.init(c1, s1);
       float acc0 = 0.f, acc1 = 0.f;
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
@@ -553,20 +590,22 @@ struct DownWave {
           h1.next();
         }
       }
-      // this lane owns fine columns x0, x0+1
-      if (writer) {
-        const float m0 = MAP ? d.m0 : a.cf.m, m1 = MAP ? d.m1 : a.cf.m;
+      A0 = fmaf(-m0, acc0, d.g0);
+      A1 = fmaf(-m1, acc1, d.g1);
+      if (!FUSE && writer) {  // this lane owns fine columns x0, x0+1
         const Plane ap(a.af + (size_t)c * a.af_cs);
         const uint32_t so = (uint32_t)r * (uint32_t)a.g.pf * 4u;
-        const float A0 = fmaf(-m0, acc0, d.g0), A1 = fmaf(-m1, acc1, d.g1);
-        if (x0 + 1 < a.g.Wf) {
-          ap.st2(make_float2(A0, A1), vx, so);
-        } else {
-          ap.st1(A0, vx, so);
-        }
+        if (two) ap.st2(make_float2(A0, A1), vx, so);
+        else ap.st1(A0, vx, so);
       }
     }
-    if (ROLE == 4 && ci >= i0) {  // wave-uniform
+    if (FUSE && ROLE == 3) {
+      pA[3][0] = A0; pA[3][1] = A1;
+      pc[3][0] = c0; pc[3][1] = c1;
+      ps[3][0] = s0; ps[3][1] = s1;
+      pm[3][0] = m0; pm[3][1] = m1;
+    }
+    if (ROLE == 4 && ci >= i0 && (!FUSE || ci < i1)) {  // wave-uniform
       const uint32_t so = (uint32_t)ci * (uint32_t)a.g.pc;
       if (writer) {
         Plane(a.gc + (size_t)c * a.gc_cs).st1(og, vcj, so * 4u);
@@ -584,9 +623,85 @@ struct DownWave {
       const Plane cp(a.csc + (size_t)c * a.csc_cs);
       if (STAGED) {
         char *row = reinterpret_cast<char *>(a.csc + (size_t)c * a.csc_cs) + (size_t)so * rec + vrun;
-        st_records_staged<NR>(row, lane, nw, q, slice);
+        st_records_staged<NR, HL>(row, lane, nw, q, slice);
       } else if (writer) {
         st_record<NR, EX>(cp, opaque(vpcj), so * rec, nr, q);
+      }
+    }
+    if (FUSE && ROLE == 4) {
+      Gm = G0;
+      G0 = Gp;
+      Gp = og;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {
+          Cm[k] = C0[k];
+          C0[k] = Cp[k];
+          Cp[k] = oc[k];
+          Sm[k] = S0[k];
+          S0[k] = Sp[k];
+          Sp[k] = os[k];
+        }
+      }
+      if (ci >= i0 + 1) finish(ci);  // wave-uniform
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        pA[0][e] = pA[2][e]; pA[1][e] = pA[3][e];
+        pc[0][e] = pc[2][e]; pc[1][e] = pc[3][e];
+        ps[0][e] = ps[2][e]; ps[1][e] = ps[3][e];
+        pm[0][e] = pm[2][e]; pm[1][e] = pm[3][e];
+      }
+      pA[2][0] = A0; pA[2][1] = A1;
+      pc[2][0] = c0; pc[2][1] = c1;
+      ps[2][0] = s0; ps[2][1] = s1;
+      pm[2][0] = m0; pm[2][1] = m1;
+    }
+  }
+
+  // FUSE: the level-l Laplacian of the output at fine rows 2 ci - 2 (even) and
+  // 2 ci - 1 (odd), from coarse rows ci - 2, ci - 1, ci of level l + 1:
+  //   L_l[O] = A - E(G_{l+1}) + m sum_k (sin E(C~_{l+1,k}) - cos E(S~_{l+1,k}))
+  // (Eq. (14)), stored in the O_l slot; the collapse then adds E(O_{l+1}).
+  __device__ inline void finish(int ci) {
+    float EG[4];
+    expand4(Gm, G0, Gp, EG);
+    Harmonics hm[4];
+    float acc[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      hm[p].init(pc[p >> 1][p & 1], ps[p >> 1][p & 1]);
+      acc[p] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      if (EX || k < K) {
+        float EC[4], ES[4];
+        expand4(Cm[k], C0[k], Cp[k], EC);
+        expand4(Sm[k], S0[k], Sp[k], ES);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          acc[p] = fmaf(hm[p].s, EC[p], fmaf(-hm[p].c, ES[p], acc[p]));
+          hm[p].next();
+        }
+      }
+    }
+    // EXPAND weights (1 6 1)/8 and (1 1)/2 per axis, by the block position
+    const float scl[4] = {1.f / 64.f, 1.f / 16.f, 1.f / 16.f, 1.f / 4.f};
+    float o[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      o[p] = fmaf(scl[p], fmaf(pm[p >> 1][p & 1], acc[p], -EG[p]), pA[p >> 1][p & 1]);
+      asm volatile("" : "+v"(o[p]));  // keeps the arithmetic next to its lane shifts
+    }
+    if (!writer) return;
+    const Plane op(a.af + (size_t)c * a.af_cs);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = 2 * ci - 2 + q;
+      if (r >= 2 * i0 && r < 2 * i1 && r < a.g.Hf) {
+        const uint32_t so = (uint32_t)r * (uint32_t)a.g.pf * 4u;
+        if (two) op.st2(make_float2(o[2 * q], o[2 * q + 1]), vx, so);
+        else op.st1(o[2 * q], vx, so);
       }
     }
   }
@@ -597,12 +712,15 @@ struct DownWave {
   // the register peak that of one row plus the prefetched next row.
   template <bool BORDER>
   __device__ inline void stream() {
+    // FUSE also needs coarse rows i0 - 1 and i1 (EXPAND halo): one coarse row
+    // more on each side
+    const int first = FUSE ? i0 - 2 : i0 - 1, last = FUSE ? i1 + 1 : i1;
     RowIn A, B;
-    load<BORDER>(A, 2 * i0 - 2);
-    load<BORDER>(B, 2 * i0 - 1);
+    load<BORDER>(A, 2 * first);
+    load<BORDER>(B, 2 * first + 1);
     ready<BORDER>(A);
-    process<0>(A, 2 * i0 - 2, i0 - 1);
-    for (int i = i0 - 1; i < i1; ++i) {
+    process<0>(A, 2 * first, first);
+    for (int i = first; i < last; ++i) {
       load<BORDER>(A, 2 * i + 2);
       ready<BORDER>(B);
       process<3>(B, 2 * i + 1, i);
@@ -618,9 +736,9 @@ struct DownWave {
   }
 };
 
-template <int ST, int KM, bool EX, bool L0, bool MAP>
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownArgs a) {
-  using W = DownWave<ST, KM, EX, L0, MAP>;
+  using W = DownWave<ST, KM, EX, L0, MAP, FUSE>;
   constexpr int SLICE = W::SLICE;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * SLICE];
   int lane, strip, seg, c;
@@ -629,11 +747,11 @@ __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownA
   w.run();
 }
 
-template <int ST, int KM, bool EX, bool L0, bool MAP>
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM))
 down_batch_kernel(const DownArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n,
                   uint32_t total) {
-  using W = DownWave<ST, KM, EX, L0, MAP>;
+  using W = DownWave<ST, KM, EX, L0, MAP, FUSE>;
   constexpr int SLICE = W::SLICE;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * SLICE];
   const int lane = threadIdx.x & 63;
@@ -649,21 +767,128 @@ down_batch_kernel(const DownArgs *__restrict__ jobs, const uint32_t *__restrict_
 }
 
 // --------------------------------------------------------------------------
+// Collapse at levels l >= 1 (Eq. (4)): O_l = L_l[O] + EXPAND(O_{l+1}), in place
+// in the O_l slot (which holds L_l[O] from down(l)); O_{l+1} = G_{l+1} when
+// level l + 1 is the top.  One plane in, one plane out.  Standard strips.
+// --------------------------------------------------------------------------
+struct CollapseWave {
+  const UpArgs &a;
+  int i0, i1, x0;
+  bool writer, two, border;
+  uint32_t vcj, vx, vxa, vxb;
+  const float *oc;
+  float *outp;
+
+  __device__ CollapseWave(const UpArgs &args, int lane, int c, int strip, int seg) : a(args) {
+    const Geom &g = a.g;
+    const int j = strip * 62 + lane - 1;
+    vcj = (uint32_t)cfold(j, g.Wc, g.Wf) * 4u;
+    i0 = seg * g.S;
+    i1 = min(i0 + g.S, g.Hc);
+    writer = lane >= 1 && lane <= 62 && j < g.Wc;
+    border = sgpr(border_strip(strip, g.Wf));
+    x0 = 2 * j;
+    two = x0 + 1 < g.Wf;
+    vx = (uint32_t)max(x0, 0) * 4u;
+    vxa = (uint32_t)min(max(x0, 0), g.Wf - 1) * 4u;
+    vxb = (uint32_t)min(max(x0 + 1, 0), g.Wf - 1) * 4u;
+    oc = a.oc + (size_t)c * a.oc_cs;
+    outp = a.out + (size_t)c * a.out_cs;
+  }
+
+  __device__ inline float load_c(int i) const {
+    const uint32_t ci = (uint32_t)cfold(i, a.g.Hc, a.g.Hf) * (uint32_t)a.g.pc;
+    return Plane(oc).ld1(vcj, ci * 4u);
+  }
+
+  template <bool BORDER>
+  __device__ inline void load_f(float *f, int i) const {
+    const Plane op(outp);
+    const uint32_t r0 = 2 * i, r1 = min(2 * i + 1, a.g.Hf - 1);
+    const uint32_t s0 = r0 * (uint32_t)a.g.pf * 4u, s1 = r1 * (uint32_t)a.g.pf * 4u;
+    if (BORDER) {
+      f[0] = op.ld1(vxa, s0);
+      f[1] = op.ld1(vxb, s0);
+      f[2] = op.ld1(vxa, s1);
+      f[3] = op.ld1(vxb, s1);
+    } else {
+      const float2 u = op.ld2(opaque(vx), s0), v = op.ld2(opaque(vx), s1);
+      f[0] = u.x;
+      f[1] = u.y;
+      f[2] = v.x;
+      f[3] = v.y;
+    }
+  }
+
+  template <bool BORDER>
+  __device__ inline void stream() {
+    const Geom &g = a.g;
+    float Dm = load_c(i0 - 1), D0 = load_c(i0), Dp = load_c(i0 + 1);
+    float fa[4], fb[4];
+    load_f<BORDER>(fa, i0);
+    const Plane op(outp);
+    const float scl[4] = {1.f / 64.f, 1.f / 16.f, 1.f / 16.f, 1.f / 4.f};
+    for (int i = i0; i < i1; ++i) {
+      const float Dn = load_c(i + 2);
+      load_f<BORDER>(fb, i + 1 < i1 ? i + 1 : i);
+      float E[4], o[4];
+      expand4(Dm, D0, Dp, E);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        o[p] = fmaf(scl[p], E[p], fa[p]);
+        asm volatile("" : "+v"(o[p]));  // keeps the arithmetic next to its lane shifts
+      }
+      if (writer) {
+        const uint32_t r0 = 2 * i;
+        const bool row1 = (int)r0 + 1 < g.Hf;
+        const uint32_t s0 = r0 * (uint32_t)g.pf * 4u, s1 = s0 + (uint32_t)g.pf * 4u;
+        if (two) {
+          op.st2(make_float2(o[0], o[1]), vx, s0);
+          if (row1) op.st2(make_float2(o[2], o[3]), vx, s1);
+        } else {
+          op.st1(o[0], vx, s0);
+          if (row1) op.st1(o[2], vx, s1);
+        }
+      }
+      Dm = D0;
+      D0 = Dp;
+      Dp = Dn;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) fa[p] = fb[p];
+    }
+  }
+
+  __device__ inline void run() {
+    if (border) stream<true>(); else stream<false>();
+  }
+};
+
+template <int ST>
+__global__ void __launch_bounds__(256, 2) collapse_kernel(UpArgs a) {
+  int lane, strip, seg, c;
+  if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
+  CollapseWave w(a, lane, c, strip, seg);
+  w.run();
+}
+
+template <int ST>
+__global__ void __launch_bounds__(256, 2)
+collapse_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n, uint32_t total) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t stride = gridDim.x * 4u;
+  for (uint32_t w = first_wave(); w < total; w += stride) {
+    const int j = find_job(start, n, w);
+    const UpArgs &a = jobs[j];
+    int strip, seg, c;
+    job_coords(a.g, w - start[j], strip, seg, c);
+    CollapseWave wv(a, lane, c, strip, seg);
+    wv.run();
+  }
+}
+
+// --------------------------------------------------------------------------
 // up(l)
 // --------------------------------------------------------------------------
-// Unnormalised EXPAND of one plane onto the lane's 2x2 fine block from coarse
-// rows i-1, i, i+1 at the lane's column (xm, x0, xp) and the neighbour lanes'.
-// e[0..3] = (2i, 2j), (2i, 2j+1), (2i+1, 2j), (2i+1, 2j+1).
-// Written so that every neighbour value is used by exactly one add, which
-// the backend folds into a DPP add (no separate lane-shift moves).
-__device__ inline void expand4(float xm, float x0, float xp, float *e) {
-  const float ve = fmaf(6.f, x0, xm + xp);
-  const float vo = x0 + xp;
-  e[1] = from_right(ve) + ve;                  // ve_j + ve_{j+1}
-  e[0] = fmaf(5.f, ve, from_left(ve) + e[1]);  // ve_{j-1} + 6 ve_j + ve_{j+1}
-  e[3] = from_right(vo) + vo;
-  e[2] = fmaf(5.f, vo, from_left(vo) + e[3]);
-}
 
 // RW: re-parameterisation; the resident records carry the previous alpha~_k
 // and every term is reweighted by wt[k] (new / previous alpha~_k).
@@ -955,7 +1180,7 @@ __global__ void __launch_bounds__(256) half_kernel(HalfArgs a) {
 // --------------------------------------------------------------------------
 // Host-side launch sequence of one job.
 // --------------------------------------------------------------------------
-inline Geom make_geom(const Level &f, const Level &cl, int C, int S) {
+inline Geom make_geom(const Level &f, const Level &cl, int C, int S, int sw) {
   Geom g;
   g.Wf = f.w;
   g.Hf = f.h;
@@ -963,7 +1188,7 @@ inline Geom make_geom(const Level &f, const Level &cl, int C, int S) {
   g.Hc = cl.h;
   g.pf = f.pitch;
   g.pc = cl.pitch;
-  g.nstrips = (cl.w + 61) / 62;
+  g.nstrips = (cl.w + sw - 1) / sw;
   g.S = S;
   g.nsegs = (cl.h + S - 1) / S;
   g.C = C;
@@ -973,14 +1198,32 @@ inline Geom make_geom(const Level &f, const Level &cl, int C, int S) {
 // Rows per wave segment.  Shorter segments give more waves (latency hiding,
 // fewer idle SIMDs in the last round) but re-read more halo rows; the target
 // wave count of each pass kind is a tuning parameter.
-inline int pick_segment(const Level &cl, int C, long target) {
-  const long strips = (cl.w + 61) / 62;
+inline int pick_segment(const Level &cl, int C, long target, int sw) {
+  const long strips = (cl.w + sw - 1) / sw;
   int S = 64;
   while (S > 1 && strips * ((cl.h + S - 1) / S) * C < target) S /= 2;
   return S;
 }
 
 inline long geom_waves(const Geom &g) { return (long)g.nstrips * g.nsegs * g.C; }
+
+// Levels l >= 1 of a job whose level l holds at least this many samples (all
+// channels) run the fused form: down(l) finishes L_l[O] and up(l) is the
+// one-plane collapse.  Smaller levels are latency-bound: there the two extra
+// coarse halo rows of every fused down wave cost more than the collapse saves,
+// and they keep the separate form (down(l) stores A_l, up(l) does the EXPAND
+// products and the collapse).  A property of the job alone, so that a job's
+// result does not depend on the jobs batched with it.
+constexpr double kFuseMinSamples = 1 << 20;
+inline bool fused_level(const JobPlan &P, int l) { return l >= 1 && (double)P.lv[l].n * P.C >= kFuseMinSamples; }
+
+// Geometry of pass down(l) / up(l) of a job: coarse columns per strip (the
+// fused down(l) uses strips of 60) and the tuned segment length.
+inline Geom pass_geom(const JobPlan &P, int l, bool down, const Tuning &tu) {
+  const int kind = down ? (l == 0 ? kTuneDown0 : kTuneDown) : (l == 0 ? kTuneUp0 : kTuneUp);
+  const int sw = down && fused_level(P, l) ? 60 : 62;
+  return make_geom(P.lv[l], P.lv[l + 1], P.C, pick_segment(P.lv[l + 1], P.C, tu.p[kind], sw), sw);
+}
 
 inline dim3 grid_for(const Geom &g) { return dim3((unsigned)((geom_waves(g) + 3) / 4), 1, 1); }
 
@@ -1007,8 +1250,7 @@ inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const
   a.mc = M(l + 1);
   a.af = l == 0 ? nullptr : (float *)(ws + lv[l].off_o);
   a.af_cs = lv[l].g_cstride;
-  a.g = make_geom(lv[l], lv[l + 1], P.C,
-                  pick_segment(lv[l + 1], P.C, tu.p[l == 0 ? kTuneDown0 : kTuneDown]));
+  a.g = pass_geom(P, l, true, tu);
   a.cf = P.coefs;
   return a;
 }
@@ -1032,7 +1274,7 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
   a.csc_cs = lv[l + 1].cs_cstride * dwp;
   a.out = l == 0 ? P.out : (float *)(ws + lv[l].off_o);
   a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
-  a.g = make_geom(lv[l], lv[l + 1], P.C, pick_segment(lv[l + 1], P.C, tu.p[l == 0 ? kTuneUp0 : kTuneUp]));
+  a.g = pass_geom(P, l, false, tu);
   a.cf = P.coefs;
   return a;
 }
@@ -1049,9 +1291,10 @@ inline double up_bytes(const JobPlan &P, int l, int dwp) {
   const Level *lv = P.lv;
   const double pb = 4.0 * dwp * P.K, C = P.C, mapb = P.m_map ? 4.0 : 0.0;
   const bool hasd = l + 1 < P.levels - 1;
+  if (fused_level(P, l)) return C * (8.0 * lv[l].n + 4.0 * lv[l + 1].n);  // L_l, O_l; O_{l+1} (or G_{l+1})
   const double fine = l == 0 ? 4.0 : 8.0;               // I, or A_l and G_l
   const double coarse = 4.0 + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
-  return C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n) + mapb * lv[l].n;
+  return C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n) + mapb * lv[l].n;  // + O_l written
 }
 
 template <int ST, int KM, bool EX, bool MAP>
@@ -1064,15 +1307,20 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
   for (int l = 0; l + 1 < L; ++l) {
     const DownArgs a = make_down_args(P, l, ws, dwp, tu);
     pre();
-    if (l == 0) down_kernel<ST, KM, EX, true, MAP><<<grid_for(a.g), blk, 0, st>>>(a);
-    else down_kernel<ST, KM, EX, false, MAP><<<grid_for(a.g), blk, 0, st>>>(a);
+    if (l == 0) down_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
+    else if (fused_level(P, l)) down_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
+    else down_kernel<ST, KM, EX, false, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
     post(kDownNames[l], down_bytes(P, l, dwp));
   }
   for (int l = L - 2; l >= 0; --l) {
     const UpArgs a = make_up_args(P, l, ws, dwp, tu);
     const bool hasd = a.oc != nullptr;
     pre();
-    if (l == 0) {
+    if (fused_level(P, l)) {
+      UpArgs ca = a;
+      if (!hasd) ca.oc = ca.gc;  // O_{l+1} is G_{l+1} at the top
+      collapse_kernel<ST><<<grid_for(ca.g), blk, 0, st>>>(ca);
+    } else if (l == 0) {
       if (hasd) up_kernel<ST, KM, EX, true, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
       else up_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
     } else {
@@ -1192,12 +1440,12 @@ hipError_t launch_batch_typed(const BatchLaunch &b, char *ws, hipStream_t st, co
   const uint32_t *start = (const uint32_t *)(ws + b.start_off);
   if (b.kind == 0) {
     const DownArgs *args = (const DownArgs *)(ws + b.args_off);
-#define FLLF_DOWN(L0)                                                                   \
+#define FLLF_DOWN(L0, FUSE)                                                             \
   {                                                                                     \
-    auto k = down_batch_kernel<ST, KM, EX, L0, MAP>;                                    \
+    auto k = down_batch_kernel<ST, KM, EX, L0, MAP, FUSE>;                              \
     k<<<batch_grid(b, (const void *)k, tu), blk, 0, st>>>(args, start, b.njobs, b.waves); \
   }
-    if (b.l0) FLLF_DOWN(true) else FLLF_DOWN(false)
+    if (b.l0) FLLF_DOWN(true, false) else if (b.fuse) FLLF_DOWN(false, true) else FLLF_DOWN(false, false)
 #undef FLLF_DOWN
   } else {
     const UpArgs *args = (const UpArgs *)(ws + b.args_off);
@@ -1206,6 +1454,7 @@ hipError_t launch_batch_typed(const BatchLaunch &b, char *ws, hipStream_t st, co
     auto k = up_batch_kernel<ST, KM, EX, L0, MAP, HASD>;                                \
     k<<<batch_grid(b, (const void *)k, tu), blk, 0, st>>>(args, start, b.njobs, b.waves); \
   }
+    // the product-sum and collapse (fused levels run collapse_batch_kernel)
     if (b.l0) {
       if (b.hasd) FLLF_UP(true, true) else FLLF_UP(true, false)
     } else {
@@ -1224,6 +1473,12 @@ hipError_t launch_batch_storage(const BatchSchedule &s, char *ws, hipStream_t st
     hipError_t e = hipSuccess;
     if (b.kind == 2) {
       e = hipMemcpyAsync(b.copy_dst, b.copy_src, b.copy_bytes, hipMemcpyDeviceToDevice, st);
+    } else if (b.kind == 1 && b.fuse) {  // the collapse does not depend on K
+      const UpArgs *args = (const UpArgs *)(ws + b.args_off);
+      const uint32_t *start = (const uint32_t *)(ws + b.start_off);
+      auto k = collapse_batch_kernel<ST>;
+      k<<<batch_grid(b, (const void *)k, tu), dim3(256, 1, 1), 0, st>>>(args, start, b.njobs, b.waves);
+      e = hipGetLastError();
     } else {
 #define FLLF_B(KM, EX) \
   e = b.map ? launch_batch_typed<ST, KM, EX, true>(b, ws, st, tu) : launch_batch_typed<ST, KM, EX, false>(b, ws, st, tu)
