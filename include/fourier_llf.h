@@ -127,9 +127,11 @@ fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_
 
 /* Launch-shape parameters of a context (index: meaning):
  *   FLLF_TUNE_DOWN0, FLLF_TUNE_DOWN, FLLF_TUNE_UP0, FLLF_TUNE_UP: the number of
- *     waves the REDUCE pass from level 0 / from levels >= 1 and the collapse
- *     pass to level 0 / to levels >= 1 aim for when they split their rows into
- *     segments (more waves = shorter segments = more halo rows re-read);
+ *     waves a pass aims for when it splits its rows into segments (more waves =
+ *     shorter segments = more halo rows re-read): the REDUCE pass from level 0;
+ *     from levels >= 1; the up passes that evaluate the product-sum of Eq. (14)
+ *     (to level 0, to levels below 2^20 samples, and all re-parameterised
+ *     passes); and the one-plane collapse to the larger levels >= 1;
  *   FLLF_TUNE_GRID_CAP: 0 = a batched launch has one wave per work item; c > 0
  *     = at most c times the blocks resident on the device at once, each wave
  *     looping over work items (persistent launch). */

@@ -176,6 +176,7 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
   p->levels = job.levels;
   p->K = job.K;
   p->C = job.channels;
+  p->dwp = storage == FLLF_STORE_F32 ? 2 : 1;
   p->in = job.in;
   p->out = job.out;
   p->m_map = job.m_map;

@@ -48,6 +48,7 @@ struct Level {
 
 struct JobPlan {
   int levels, K, C;
+  int dwp;           // dwords per stored (C~, S~) pair: 2 (float32) or 1 (16-bit)
   Level lv[kMaxLevels];
   size_t bytes;      // workspace bytes of this job
   Coefs coefs;

@@ -32,6 +32,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fllf_internal.h"
 
 namespace fllf {
@@ -413,6 +415,21 @@ __device__ inline bool border_strip(int strip, int Wf, int sw = 62, int hl = 1) 
 // --------------------------------------------------------------------------
 // down(l)
 // --------------------------------------------------------------------------
+// State of the fused down pass: coarse rows ci-2, ci-1, ci (G and the
+// at_k-weighted pairs) and, for fine rows 2ci-2 .. 2ci+1 at the lane's two
+// columns, the level-l half A, cos/sin(omega_1 g) and the boost, waiting for
+// coarse row ci.  A separate member so that the other passes carry none of it.
+template <int KM>
+struct FuseRing {
+  float Gm, G0, Gp, Cm[KM], C0[KM], Cp[KM], Sm[KM], S0[KM], Sp[KM];
+  float pA[4][2], pc[4][2], ps[4][2], pm[4][2];
+};
+struct NoRing {};
+
+// Pyramid records the fused pass keeps in registers without spilling: exact
+// K loops of at most 16 dwords per record (float32 K <= 8, 16-bit K <= 16).
+constexpr bool fusable(int K, int dwp) { return (K == 4 || K == 8 || K == 16) && K * dwp <= 16; }
+
 template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE>
 struct DownWave {
   static_assert(!(L0 && FUSE), "level 0 has no Laplacian to finish");
@@ -446,11 +463,7 @@ struct DownWave {
   const uint32_t *csf;
   float PG0, PG1, PM0, PM1;
   float PC0[KM], PC1[KM], PS0[KM], PS1[KM];
-  // FUSE: coarse rows ci-2, ci-1, ci (G and the at_k-weighted pairs) ...
-  float Gm, G0, Gp, Cm[KM], C0[KM], Cp[KM], Sm[KM], S0[KM], Sp[KM];
-  // ... and, for fine rows 2ci-2 .. 2ci+1 at columns x0, x0+1: the level-l half
-  // A, cos/sin(omega_1 g) and the boost, waiting for coarse row ci
-  float pA[4][2], pc[4][2], ps[4][2], pm[4][2];
+  typename std::conditional<FUSE, FuseRing<KM>, NoRing>::type z;
 
   __device__ DownWave(const DownArgs &args, int lane_, int c_, int strip, int seg, uint32_t *slice_)
       : a(args) {
@@ -470,13 +483,13 @@ struct DownWave {
     x0 = 2 * j;
     two = x0 + 1 < a.g.Wf;
     vspan = border ? 0u : (uint32_t)(2 * (strip * SW - HL)) * rec;
-    if (FUSE) {
-      Gm = G0 = Gp = 0.f;
+    if constexpr (FUSE) {
+      z.Gm = z.G0 = z.Gp = 0.f;
 #pragma unroll
-      for (int k = 0; k < KM; ++k) Cm[k] = C0[k] = Cp[k] = Sm[k] = S0[k] = Sp[k] = 0.f;
+      for (int k = 0; k < KM; ++k) z.Cm[k] = z.C0[k] = z.Cp[k] = z.Sm[k] = z.S0[k] = z.Sp[k] = 0.f;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        for (int e = 0; e < 2; ++e) pA[q][e] = pc[q][e] = ps[q][e] = pm[q][e] = 0.f;
+        for (int e = 0; e < 2; ++e) z.pA[q][e] = z.pc[q][e] = z.ps[q][e] = z.pm[q][e] = 0.f;
     }
     const int f0 = reflect(x0, a.g.Wf), f1 = reflect(x0 + 1, a.g.Wf);
     vx = (uint32_t)max(x0, 0) * 4u;
@@ -599,11 +612,11 @@ struct DownWave {
         else ap.st1(A0, vx, so);
       }
     }
-    if (FUSE && ROLE == 3) {
-      pA[3][0] = A0; pA[3][1] = A1;
-      pc[3][0] = c0; pc[3][1] = c1;
-      ps[3][0] = s0; ps[3][1] = s1;
-      pm[3][0] = m0; pm[3][1] = m1;
+    if constexpr (FUSE && ROLE == 3) {
+      z.pA[3][0] = A0; z.pA[3][1] = A1;
+      z.pc[3][0] = c0; z.pc[3][1] = c1;
+      z.ps[3][0] = s0; z.ps[3][1] = s1;
+      z.pm[3][0] = m0; z.pm[3][1] = m1;
     }
     if (ROLE == 4 && ci >= i0 && (!FUSE || ci < i1)) {  // wave-uniform
       const uint32_t so = (uint32_t)ci * (uint32_t)a.g.pc;
@@ -628,33 +641,33 @@ struct DownWave {
         st_record<NR, EX>(cp, opaque(vpcj), so * rec, nr, q);
       }
     }
-    if (FUSE && ROLE == 4) {
-      Gm = G0;
-      G0 = Gp;
-      Gp = og;
+    if constexpr (FUSE && ROLE == 4) {
+      z.Gm = z.G0;
+      z.G0 = z.Gp;
+      z.Gp = og;
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
-          Cm[k] = C0[k];
-          C0[k] = Cp[k];
-          Cp[k] = oc[k];
-          Sm[k] = S0[k];
-          S0[k] = Sp[k];
-          Sp[k] = os[k];
+          z.Cm[k] = z.C0[k];
+          z.C0[k] = z.Cp[k];
+          z.Cp[k] = oc[k];
+          z.Sm[k] = z.S0[k];
+          z.S0[k] = z.Sp[k];
+          z.Sp[k] = os[k];
         }
       }
       if (ci >= i0 + 1) finish(ci);  // wave-uniform
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        pA[0][e] = pA[2][e]; pA[1][e] = pA[3][e];
-        pc[0][e] = pc[2][e]; pc[1][e] = pc[3][e];
-        ps[0][e] = ps[2][e]; ps[1][e] = ps[3][e];
-        pm[0][e] = pm[2][e]; pm[1][e] = pm[3][e];
+        z.pA[0][e] = z.pA[2][e]; z.pA[1][e] = z.pA[3][e];
+        z.pc[0][e] = z.pc[2][e]; z.pc[1][e] = z.pc[3][e];
+        z.ps[0][e] = z.ps[2][e]; z.ps[1][e] = z.ps[3][e];
+        z.pm[0][e] = z.pm[2][e]; z.pm[1][e] = z.pm[3][e];
       }
-      pA[2][0] = A0; pA[2][1] = A1;
-      pc[2][0] = c0; pc[2][1] = c1;
-      ps[2][0] = s0; ps[2][1] = s1;
-      pm[2][0] = m0; pm[2][1] = m1;
+      z.pA[2][0] = A0; z.pA[2][1] = A1;
+      z.pc[2][0] = c0; z.pc[2][1] = c1;
+      z.ps[2][0] = s0; z.ps[2][1] = s1;
+      z.pm[2][0] = m0; z.pm[2][1] = m1;
     }
   }
 
@@ -664,20 +677,20 @@ struct DownWave {
   // (Eq. (14)), stored in the O_l slot; the collapse then adds E(O_{l+1}).
   __device__ inline void finish(int ci) {
     float EG[4];
-    expand4(Gm, G0, Gp, EG);
+    expand4(z.Gm, z.G0, z.Gp, EG);
     Harmonics hm[4];
     float acc[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      hm[p].init(pc[p >> 1][p & 1], ps[p >> 1][p & 1]);
+      hm[p].init(z.pc[p >> 1][p & 1], z.ps[p >> 1][p & 1]);
       acc[p] = 0.f;
     }
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
       if (EX || k < K) {
         float EC[4], ES[4];
-        expand4(Cm[k], C0[k], Cp[k], EC);
-        expand4(Sm[k], S0[k], Sp[k], ES);
+        expand4(z.Cm[k], z.C0[k], z.Cp[k], EC);
+        expand4(z.Sm[k], z.S0[k], z.Sp[k], ES);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
           acc[p] = fmaf(hm[p].s, EC[p], fmaf(-hm[p].c, ES[p], acc[p]));
@@ -690,7 +703,7 @@ struct DownWave {
     float o[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      o[p] = fmaf(scl[p], fmaf(pm[p >> 1][p & 1], acc[p], -EG[p]), pA[p >> 1][p & 1]);
+      o[p] = fmaf(scl[p], fmaf(z.pm[p >> 1][p & 1], acc[p], -EG[p]), z.pA[p >> 1][p & 1]);
       asm volatile("" : "+v"(o[p]));  // keeps the arithmetic next to its lane shifts
     }
     if (!writer) return;
@@ -1208,19 +1221,25 @@ inline int pick_segment(const Level &cl, int C, long target, int sw) {
 inline long geom_waves(const Geom &g) { return (long)g.nstrips * g.nsegs * g.C; }
 
 // Levels l >= 1 of a job whose level l holds at least this many samples (all
-// channels) run the fused form: down(l) finishes L_l[O] and up(l) is the
+// channels), with records the fused pass can hold (fusable), run the fused form: down(l) finishes L_l[O] and up(l) is the
 // one-plane collapse.  Smaller levels are latency-bound: there the two extra
 // coarse halo rows of every fused down wave cost more than the collapse saves,
 // and they keep the separate form (down(l) stores A_l, up(l) does the EXPAND
 // products and the collapse).  A property of the job alone, so that a job's
 // result does not depend on the jobs batched with it.
 constexpr double kFuseMinSamples = 1 << 20;
-inline bool fused_level(const JobPlan &P, int l) { return l >= 1 && (double)P.lv[l].n * P.C >= kFuseMinSamples; }
+inline bool fused_level(const JobPlan &P, int l) {
+  return l >= 1 && fusable(P.K, P.dwp) && (double)P.lv[l].n * P.C >= kFuseMinSamples;
+}
 
 // Geometry of pass down(l) / up(l) of a job: coarse columns per strip (the
-// fused down(l) uses strips of 60) and the tuned segment length.
-inline Geom pass_geom(const JobPlan &P, int l, bool down, const Tuning &tu) {
-  const int kind = down ? (l == 0 ? kTuneDown0 : kTuneDown) : (l == 0 ? kTuneUp0 : kTuneUp);
+// fused down(l) uses strips of 60) and the tuned segment length.  The up passes
+// that evaluate the product-sum (level 0, levels that are not fused, and every
+// re-parameterised pass) share one segment target; the one-plane collapse of
+// the fused levels has its own.
+inline Geom pass_geom(const JobPlan &P, int l, bool down, const Tuning &tu, bool reparam = false) {
+  const bool collapse = !down && !reparam && fused_level(P, l);
+  const int kind = down ? (l == 0 ? kTuneDown0 : kTuneDown) : (collapse ? kTuneUp : kTuneUp0);
   const int sw = down && fused_level(P, l) ? 60 : 62;
   return make_geom(P.lv[l], P.lv[l + 1], P.C, pick_segment(P.lv[l + 1], P.C, tu.p[kind], sw), sw);
 }
@@ -1255,7 +1274,7 @@ inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const
   return a;
 }
 
-inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tuning &tu) {
+inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tuning &tu, bool reparam = false) {
   const Level *lv = P.lv;
   const int L = P.levels;
   const bool map = P.m_map != nullptr;
@@ -1274,7 +1293,7 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
   a.csc_cs = lv[l + 1].cs_cstride * dwp;
   a.out = l == 0 ? P.out : (float *)(ws + lv[l].off_o);
   a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
-  a.g = pass_geom(P, l, false, tu);
+  a.g = pass_geom(P, l, false, tu, reparam);
   a.cf = P.coefs;
   return a;
 }
@@ -1297,6 +1316,14 @@ inline double up_bytes(const JobPlan &P, int l, int dwp) {
   return C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n) + mapb * lv[l].n;  // + O_l written
 }
 
+// The fused down pass exists for the fusable K loops only (fused_level never
+// selects it for the others).
+template <int ST, int KM, bool EX, bool MAP>
+void launch_fused_down(const DownArgs &a, hipStream_t st) {
+  if constexpr (EX && fusable(KM, PairStore<ST>::DW))
+    down_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), dim3(256, 1, 1), 0, st>>>(a);
+}
+
 template <int ST, int KM, bool EX, bool MAP>
 hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *hook, const Tuning &tu) {
   const int L = P.levels;
@@ -1308,7 +1335,7 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
     const DownArgs a = make_down_args(P, l, ws, dwp, tu);
     pre();
     if (l == 0) down_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
-    else if (fused_level(P, l)) down_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
+    else if (fused_level(P, l)) launch_fused_down<ST, KM, EX, MAP>(a, st);
     else down_kernel<ST, KM, EX, false, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
     post(kDownNames[l], down_bytes(P, l, dwp));
   }
@@ -1388,7 +1415,7 @@ hipError_t launch_reparam_typed(const JobPlan &P, char *ws, hipStream_t st, Laun
     if (hook) hook->after(st, kHalfNames[l], (double)P.C * lv.n * (8.0 + pb));
   }
   for (int l = L - 2; l >= 0; --l) {
-    const UpArgs a = make_up_args(P, l, ws, dwp, tu);
+    const UpArgs a = make_up_args(P, l, ws, dwp, tu, true);
     const bool hasd = a.oc != nullptr;
     if (hook) hook->before(st);
     if (l == 0) {
@@ -1445,7 +1472,13 @@ hipError_t launch_batch_typed(const BatchLaunch &b, char *ws, hipStream_t st, co
     auto k = down_batch_kernel<ST, KM, EX, L0, MAP, FUSE>;                              \
     k<<<batch_grid(b, (const void *)k, tu), blk, 0, st>>>(args, start, b.njobs, b.waves); \
   }
-    if (b.l0) FLLF_DOWN(true, false) else if (b.fuse) FLLF_DOWN(false, true) else FLLF_DOWN(false, false)
+    if (b.l0) {
+      FLLF_DOWN(true, false)
+    } else if (b.fuse) {
+      if constexpr (EX && fusable(KM, PairStore<ST>::DW)) FLLF_DOWN(false, true)
+    } else {
+      FLLF_DOWN(false, false)
+    }
 #undef FLLF_DOWN
   } else {
     const UpArgs *args = (const UpArgs *)(ws + b.args_off);

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import fourier_llf_ref as ref
-from paper_2206_04681_amd.synth import UHD_RGB
+from paper_2206_04681_amd.synth import UHD_RGB, synth_image
 
 pytestmark = pytest.mark.gpu
 
@@ -45,6 +45,50 @@ def test_uhd_rgb_against_oracle(uhd, storage, K):
     want = _oracle_channel0(img, K)
     err, p = ref.max_abs(got[0], want), ref.psnr(got[0], want)
     print(f"\n3840x2160 RGB, K={K}, {storage} pyramids: channel 0 max-abs {err:.3e}, PSNR {p:.1f} dB")
+    tol, min_psnr = BOUNDS[storage]
+    assert err <= tol
+    if min_psnr is not None:
+        assert p >= min_psnr
+
+
+# Fused levels at odd sizes: 2730x2186 RGB has levels 1 (1365x1093) and 2
+# (683x547) above 2^20 samples over its channels, both odd in both directions,
+# so the fused down pass meets ragged strips and the EXPAND folds at the right
+# and bottom edges; level 3 and up keep the separate passes.
+ODD = (3, 2186, 2730)
+
+
+@pytest.fixture(scope="module")
+def odd_rgb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c, h, w = ODD
+    img = synth_image(h, w, c, seed=17, n_rect=30, n_disk=30, noise=0.01)
+    return torch, img, torch.from_numpy(img).cuda()
+
+
+@pytest.mark.parametrize("storage,K,use_map", [("f32", 8, False), ("f32", 4, False), ("f32", 8, True),
+                                               ("f16", 16, False)])
+def test_fused_levels_odd_sizes_against_oracle(odd_rgb, storage, K, use_map):
+    torch, img, x = odd_rgb
+    from paper_2206_04681_amd.fllf import FourierLLF
+    c, h, w = ODD
+    levels, sigma, m = 6, 0.15, 2.0
+    mm = None
+    if use_map:
+        xx = np.mgrid[0:h, 0:w][1]
+        mm = (0.5 + 2.5 * xx / (w - 1)).astype(np.float32)
+    out = FourierLLF(storage).run(x, levels, sigma, m, K, m_map=None if mm is None else torch.from_numpy(mm).cuda())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0]
+    assert np.isfinite(got).all()
+    g0 = img[0].astype(np.float64)
+    if use_map:
+        want = ref.fourier_llf_adaptive(g0, levels, sigma, mm.astype(np.float64), K)
+    else:
+        want = ref.fourier_llf(g0, levels, sigma, m, K)
+    err, p = ref.max_abs(got, want), ref.psnr(got, want)
+    print(f"\n2730x2186 RGB, K={K}, {storage}, map={use_map}: channel 0 max-abs {err:.3e}, PSNR {p:.1f} dB")
     tol, min_psnr = BOUNDS[storage]
     assert err <= tol
     if min_psnr is not None:
