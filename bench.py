@@ -100,6 +100,25 @@ def step_percentiles(torch, fn, steps):
     return float(np.median(t)), float(np.percentile(t, 90))
 
 
+def cold_step_percentiles(torch, fn, steps, flush_bytes=512 << 20):
+    """Per-step device time with the 256 MB last-level cache (MALL) cold: a
+    512 MB fill before each step, outside its events, evicts what the previous
+    step left there.  Median and p90 in ms."""
+    import numpy as np
+    junk = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda")
+    t = []
+    for i in range(steps):
+        junk.fill_(float(i))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        t.append(a.elapsed_time(b))
+    del junk
+    return float(np.median(t)), float(np.percentile(t, 90))
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     """Device-to-device copy of nbytes (torch's copy kernel): GB/s of read + write."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -141,15 +160,17 @@ def run_form(torch, fllf, storage, x, w, steps, warmup):
 
     ms = time_steps(torch, step, steps, warmup)
     p50, p90 = step_percentiles(torch, step, steps)
+    cold50, cold90 = cold_step_percentiles(torch, step, steps)
     # the same launches replayed from a captured HIP graph
     g = ctx.graph([fj], workspace=ws)
     ms_graph = time_steps(torch, g.launch, steps, warmup)
     g.close()
-    log(f"{storage}: {ms:.4f} ms/step (per-step p50 {p50:.4f}, p90 {p90:.4f}; graph replay {ms_graph:.4f})")
+    log(f"{storage}: {ms:.4f} ms/step (per-step p50 {p50:.4f}, p90 {p90:.4f}; cold MALL p50 {cold50:.4f}; "
+        f"graph replay {ms_graph:.4f})")
     prof = kernel_profile(torch, ctx, step, steps)
     per_step_bytes = sum(r["bytes"] for r in prof) / steps
-    return dict(ms=ms, p50=p50, p90=p90, ms_graph=ms_graph, kernels=prof, alg_bytes_per_step=per_step_bytes,
-                ctx=ctx, out=out)
+    return dict(ms=ms, p50=p50, p90=p90, cold50=cold50, cold90=cold90, ms_graph=ms_graph, kernels=prof,
+                alg_bytes_per_step=per_step_bytes, ctx=ctx, out=out)
 
 
 def run_reparam(torch, fllf, x, w, steps, warmup, full_ms):
@@ -213,21 +234,24 @@ def run_batched(torch, fllf, storages, steps, warmup):
     return res
 
 
-def serve_once(torch, fllf, reqs, hosts, storage, arena_bytes, max_active=64):
-    """Drive the server over an open-loop request list; returns latency stats."""
+def serve_once(torch, fllf, reqs, hosts, storage, arena_bytes, max_active=64, max_outstanding=64):
+    """Drive the server over an open-loop request list; returns latency stats.
+    At most `max_outstanding` requests hold device memory (input and output) at
+    once; later arrivals wait in host memory (backpressure under overload) and
+    their latency still counts from arrival."""
     import numpy as np
     llf = fllf.FourierLLF(storage)
     srv = fllf.Server(llf, arena_bytes, max_active=max_active)
     copy, comp = torch.cuda.Stream(), torch.cuda.Stream()
     n = len(reqs)
     lat, h2d = np.zeros(n), np.zeros(n)
-    live, done_mpix, max_queued = {}, 0.0, 0
+    live, done_mpix, max_queued, max_backlog = {}, 0.0, 0, 0
     i = completed = 0
     first_done = last_done = None
     t0 = time.perf_counter()
     while completed < n:
         now = time.perf_counter() - t0
-        while i < n and reqs[i].arrival <= now:
+        while i < n and reqs[i].arrival <= now and len(live) < max_outstanding:
             r = reqs[i]
             w = r.work
             x = torch.empty((3, w.height, w.width), dtype=torch.float32, device="cuda")
@@ -239,6 +263,10 @@ def serve_once(torch, fllf, reqs, hosts, storage, arena_bytes, max_active=64):
             out = srv.submit(fllf.Job(x, w.levels, w.sigma_r, w.m, w.K), tag=i, ready_event=e1)
             live[i] = (x, out, e0, e1)
             i += 1
+        backlog = 0
+        while i + backlog < n and reqs[i + backlog].arrival <= now:
+            backlog += 1
+        max_backlog = max(max_backlog, backlog)
         srv.step(comp)
         max_queued = max(max_queued, srv.stats()["queued"])
         for t in srv.poll():
@@ -267,7 +295,8 @@ def serve_once(torch, fllf, reqs, hosts, storage, arena_bytes, max_active=64):
             "h2d_share_of_latency": round(float(h2d.sum() / lat.sum()), 3),
             "served_mpix_per_s": round(done_mpix / span, 2),
             "arena_gb": round(st["arena_bytes"] / 1e9, 3), "arena_peak_gb": round(st["arena_peak"] / 1e9, 3),
-            "max_queued": max_queued, "steps": st["steps"], "launches": st["launches"]}
+            "max_queued": max_queued, "max_host_backlog": max_backlog, "steps": st["steps"],
+            "launches": st["launches"]}
 
 
 def run_serve(torch, fllf, args):
@@ -299,8 +328,10 @@ def run_serve(torch, fllf, args):
             r = serve_once(torch, fllf, rq, hosts, "f16", budget)
             r["rate_per_s"] = rate
             sweep.append({k: r[k] for k in ("rate_per_s", "requests", "latency_ms_p50", "latency_ms_p99",
-                                            "served_mpix_per_s", "max_queued")})
-            log(f"saturation sweep {rate}/s: p50 {r['latency_ms_p50']} ms, p99 {r['latency_ms_p99']} ms")
+                                            "served_mpix_per_s", "h2d_share_of_latency", "max_queued",
+                                            "max_host_backlog")})
+            log(f"saturation sweep {rate}/s: p50 {r['latency_ms_p50']} ms, p99 {r['latency_ms_p99']} ms, "
+                f"{r['served_mpix_per_s']} MPix/s served, host backlog up to {r['max_host_backlog']}")
         res["saturation_sweep"] = sweep
     return res
 
@@ -441,6 +472,8 @@ def main():
         "ms_p50": round(main_form["p50"], 5),
         "ms_p90": round(main_form["p90"], 5),
         "ms_graph_replay": round(main_form["ms_graph"], 5),
+        "ms_cold_mall_p50": round(main_form["cold50"], 5),
+        "ms_cold_mall_p90": round(main_form["cold90"], 5),
         "step_alg_gbs": round(main_form["alg_bytes_per_step"] / (ms * 1e-3) / 1e9, 1),
         "copy_gbs_measured": round(copy_gbs, 1),
         "kernels": {k: [dict(name=r["name"], launches=r["launches"] // args.steps,
@@ -451,6 +484,7 @@ def main():
         if k != main_key:
             result[f"{k}_store"] = {"value": round(mpix / (f["ms"] * 1e-3), 2), "unit": "MPix/s",
                                     "ms_per_step": round(f["ms"], 5), "ms_graph_replay": round(f["ms_graph"], 5),
+                                    "ms_cold_mall_p50": round(f["cold50"], 5),
                                     "speedup_vs_f32": round(ms / f["ms"], 3)}
     if not args.no_reparam:
         result["reparam"] = run_reparam(torch, fllf, x, w, args.steps, args.warmup, ms)
