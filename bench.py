@@ -35,14 +35,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_uhd_rgb_k8.txt")
 
 
 def kernel_source_digest():
-    """sha256 over the native sources (kernels and launch configuration)."""
+    """sha256 over the native sources (kernels and launch configuration), with
+    comments and blank lines removed so that documentation edits keep it."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2206_04681_amd", "csrc")
     for fn in sorted(os.listdir(csrc)):
         if fn.endswith((".h", ".hip", ".cpp")):
+            text = open(os.path.join(csrc, fn), encoding="utf-8").read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
             h.update(fn.encode())
-            h.update(open(os.path.join(csrc, fn), "rb").read())
+            h.update(code.encode())
     return h.hexdigest()
 
 

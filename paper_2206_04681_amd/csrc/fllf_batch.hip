@@ -3,10 +3,13 @@
 // Every pass of the per-job sequence (down(0) .. down(L-2), then up(L-2) ..
 // up(0)) is run for all jobs that have it as one launch per kernel class; the
 // classes are the K loop (exact 4, 8, 16 or guarded 8, 16, 32), the boost map,
-// and for up(l) whether level l + 1 is the job's top.  Passes are aligned on
-// the level index l, so a job with fewer levels simply sits out the coarse
-// passes: each job still sees its own passes in its own order, and the kernels
-// are the per-job wave bodies, so a job's result does not depend on the batch.
+// whether the job's level l takes the fused form, and for the product-sum up(l)
+// whether level l + 1 is the job's top; the one-plane collapses of the fused
+// levels depend on neither K nor the map and share one launch.  Passes are
+// aligned on the level index l, so a job with fewer levels simply sits out the
+// coarse passes: each job still sees its own passes in its own order, and the
+// kernels are the per-job wave bodies, so a job's result does not depend on the
+// batch.
 //
 // The launches find their jobs in a table at the start of the workspace: per
 // launch, the argument records of its jobs and the prefix sums of their wave

@@ -60,6 +60,21 @@ def test_reparam_chain_from_same_pyramids(torch_dev):
         assert ref.max_abs(out2.cpu().numpy(), want) <= 1e-4, (sigma2, m2)
 
 
+def test_reparam_after_a_fused_run(torch_dev):
+    """1500x1100 RGB: the first run takes the fused form at level 1; the
+    re-parameterised passes read the same resident pyramids."""
+    torch = torch_dev
+    fllf, ctx, x, prev, ws, T = _setup(torch, "f32", shape=(3, 1100, 1500), L=7, K=8, sigma=0.12, m=2.0)
+    out2 = torch.empty_like(x)
+    nxt, _ = ctx._prepare(fllf.Job(x, 7, 0.2, 3.0, 8, out=out2))
+    ctx.reparam(prev, nxt, ws)
+    full = _full(torch, fllf, "f32", x, 7, 0.2, 3.0, 8, T)
+    torch.cuda.synchronize()
+    assert float((out2 - full).abs().max()) <= 2e-5
+    want = ref.fourier_llf(x[0].cpu().numpy().astype(np.float64), 7, 0.2, 3.0, 8, T=T)
+    assert ref.max_abs(out2[0].cpu().numpy(), want) <= 1e-4
+
+
 @pytest.mark.parametrize("storage,tol", [("f16", 2e-4), ("bf16", 2e-3)])
 def test_reparam_reduced_storage(torch_dev, storage, tol):
     torch = torch_dev

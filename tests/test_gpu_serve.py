@@ -23,9 +23,11 @@ REQS = [((3, 240, 320), 7, 0.1, 2.0, 8), ((1, 100, 130), 6, 0.2, 2.0, 4),
         ((3, 200, 300), 6, 0.15, -1.0, 5), ((1, 1, 1), 1, 0.2, 2.0, 4),
         ((3, 360, 480), 7, 0.25, 2.0, 4), ((1, 512, 512), 6, 0.2, 2.0, 4),
         ((3, 129, 257), 8, 0.12, 2.0, 16), ((1, 64, 64), 7, 0.2, 1.0, 8),
-        ((3, 300, 200), 6, 0.08, 2.0, 8), ((1, 700, 90), 7, 0.2, 2.0, 32)]
+        ((3, 300, 200), 6, 0.08, 2.0, 8), ((1, 700, 90), 7, 0.2, 2.0, 32),
+        # large enough for the fused form at level 1 (the second with float16 pairs only)
+        ((3, 1100, 1500), 7, 0.12, 2.0, 8), ((1, 2200, 2000), 8, 0.2, 2.0, 16)]
 # step index at which each request arrives: several join while others are mid-flight
-ARRIVE = [0, 0, 1, 3, 3, 4, 6, 9, 9, 10, 15, 22]
+ARRIVE = [0, 0, 1, 3, 3, 4, 6, 9, 9, 10, 15, 22, 2, 12]
 
 
 def _inputs(torch, seed):
