@@ -374,7 +374,8 @@ struct UpArgs {
 // false when the wave has no work.
 __device__ inline bool wave_coords(const Geom &g, int &lane, int &strip, int &seg, int &c) {
   lane = threadIdx.x & 63;
-  const int wv = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // blocks of four waves, or of one (small passes)
+  const int wv = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   strip = __builtin_amdgcn_readfirstlane(wv % g.nstrips);
   const int rest = wv / g.nstrips;
   seg = __builtin_amdgcn_readfirstlane(rest % g.nsegs);
@@ -1244,7 +1245,17 @@ inline Geom pass_geom(const JobPlan &P, int l, bool down, const Tuning &tu, bool
   return make_geom(P.lv[l], P.lv[l + 1], P.C, pick_segment(P.lv[l + 1], P.C, tu.p[kind], sw), sw);
 }
 
-inline dim3 grid_for(const Geom &g) { return dim3((unsigned)((geom_waves(g) + 3) / 4), 1, 1); }
+// Launch shape of a single-job pass: blocks of four waves, or of one wave when
+// the pass has few waves.  A small level's pass is bound by the memory pipeline
+// of the few compute units it occupies: one wave per block spreads it over four
+// times as many (4K RGB float32: down passes at levels 4-6 from 10.2-11.0 to
+// 7.3-8.8 us).  From about 800 waves on, four-wave blocks are faster again.
+constexpr long kSmallPassWaves = 512;
+inline dim3 block_for(const Geom &g) { return dim3(geom_waves(g) < kSmallPassWaves ? 64 : 256, 1, 1); }
+inline dim3 grid_for(const Geom &g) {
+  const long w = geom_waves(g);
+  return dim3((unsigned)(w < kSmallPassWaves ? w : (w + 3) / 4), 1, 1);
+}
 
 // Arguments of down(l) / up(l) of one planned job whose workspace is ws.
 inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const Tuning &tu) {
@@ -1321,7 +1332,7 @@ inline double up_bytes(const JobPlan &P, int l, int dwp) {
 template <int ST, int KM, bool EX, bool MAP>
 void launch_fused_down(const DownArgs &a, hipStream_t st) {
   if constexpr (EX && fusable(KM, PairStore<ST>::DW))
-    down_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), dim3(256, 1, 1), 0, st>>>(a);
+    down_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
 }
 
 template <int ST, int KM, bool EX, bool MAP>
@@ -1330,13 +1341,12 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
   const int dwp = PairStore<ST>::DW;  // dwords per pair
   auto pre = [&]() { if (hook) hook->before(st); };
   auto post = [&](const char *name, double bytes) { if (hook) hook->after(st, name, bytes); };
-  const dim3 blk(256, 1, 1);
   for (int l = 0; l + 1 < L; ++l) {
     const DownArgs a = make_down_args(P, l, ws, dwp, tu);
     pre();
-    if (l == 0) down_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
+    if (l == 0) down_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
     else if (fused_level(P, l)) launch_fused_down<ST, KM, EX, MAP>(a, st);
-    else down_kernel<ST, KM, EX, false, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
+    else down_kernel<ST, KM, EX, false, MAP, false><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
     post(kDownNames[l], down_bytes(P, l, dwp));
   }
   for (int l = L - 2; l >= 0; --l) {
@@ -1346,13 +1356,13 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
     if (fused_level(P, l)) {
       UpArgs ca = a;
       if (!hasd) ca.oc = ca.gc;  // O_{l+1} is G_{l+1} at the top
-      collapse_kernel<ST><<<grid_for(ca.g), blk, 0, st>>>(ca);
+      collapse_kernel<ST><<<grid_for(ca.g), block_for(ca.g), 0, st>>>(ca);
     } else if (l == 0) {
-      if (hasd) up_kernel<ST, KM, EX, true, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
-      else up_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
+      if (hasd) up_kernel<ST, KM, EX, true, MAP, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+      else up_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
     } else {
-      if (hasd) up_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), blk, 0, st>>>(a);
-      else up_kernel<ST, KM, EX, false, MAP, false><<<grid_for(a.g), blk, 0, st>>>(a);
+      if (hasd) up_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+      else up_kernel<ST, KM, EX, false, MAP, false><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
     }
     post(kUpNames[l], up_bytes(P, l, dwp));
   }
@@ -1419,11 +1429,11 @@ hipError_t launch_reparam_typed(const JobPlan &P, char *ws, hipStream_t st, Laun
     const bool hasd = a.oc != nullptr;
     if (hook) hook->before(st);
     if (l == 0) {
-      if (hasd) up_kernel<ST, KM, true, true, false, true, true><<<grid_for(a.g), blk, 0, st>>>(a);
-      else up_kernel<ST, KM, true, true, false, false, true><<<grid_for(a.g), blk, 0, st>>>(a);
+      if (hasd) up_kernel<ST, KM, true, true, false, true, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+      else up_kernel<ST, KM, true, true, false, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
     } else {
-      if (hasd) up_kernel<ST, KM, true, false, false, true, true><<<grid_for(a.g), blk, 0, st>>>(a);
-      else up_kernel<ST, KM, true, false, false, false, true><<<grid_for(a.g), blk, 0, st>>>(a);
+      if (hasd) up_kernel<ST, KM, true, false, false, true, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+      else up_kernel<ST, KM, true, false, false, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
     }
     if (hook) hook->after(st, kUpNames[l], up_bytes(P, l, dwp));
   }
