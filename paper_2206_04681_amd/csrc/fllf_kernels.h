@@ -15,14 +15,21 @@
 //             = L_l[O] of Eq. (14) plus the collapse step of Eq. (4); at level 0,
 //             A_0 = I and the level-0 Fourier terms vanish (first case of Eq. (14)).
 //
+// Fused levels (large levels >= 1, see fused_level): down(l) also finishes
+// L_l[O] = A_l - EXPAND(G_{l+1}) + m sum_k at_k (sin EXPAND(C~) - cos EXPAND(S~))
+// from the coarse rows it has just reduced, and up(l) is the one-plane collapse
+// O_l = L_l[O] + EXPAND(O_{l+1}).
+//
 // The Fourier pyramids are stored pre-multiplied by at_k = alpha~_k (REDUCE and
 // EXPAND are linear, so every level carries the same factor); the product-sum
 // then needs no per-term multiply.  The K (C~, S~) pairs of a pixel form one
 // contiguous record, so a wave reads one contiguous run of records per row.
 //
-// Memory-bound multi-plane stencils; no LDS and no MFMA.  One wave64 owns a
-// strip of 62 coarse columns (lane t <-> coarse column 62 s + t - 1; lanes 0 and
-// 63 are halo) and streams down a segment of coarse rows.  Horizontal taps come
+// Memory-bound multi-plane stencils; no MFMA, and LDS only as wave-private
+// staging that turns record rows into 1 KB accesses.  One wave64 owns a strip of
+// 62 coarse columns (lane t <-> coarse column 62 s + t - 1; lanes 0 and 63 are
+// halo; the fused down pass uses 60 columns and two halo lanes a side) and
+// streams down a segment of coarse rows.  Horizontal taps come
 // from neighbouring lanes by DPP wave shifts; vertical taps are register
 // running sums.  Each row's loads are issued one row ahead.  All memory access
 // is through buffer resources: plane bases and row offsets live in scalar
@@ -147,8 +154,8 @@ __device__ inline void st_record(const Plane &p, uint32_t voff, uint32_t soff, i
     if (EX || i < n) p.stu(d[i], voff + 4u * i, soff);
 }
 
-// Stores the records of the wave's writer lanes (lanes 1 .. nw, NR dwords each,
-// NR a multiple of 4) to one contiguous run starting at byte voff0 + soff.  The
+// Stores the records of the wave's writer lanes (lanes FIRST .. FIRST + nw - 1,
+// NR dwords each, NR a multiple of 4) to one contiguous run starting at `row`.  The
 // records go through the wave's LDS slice (lane L's record at L * (NR + 4)
 // dwords; the pad spreads the lanes over the LDS banks) so that every store
 // instruction writes 64 consecutive 16-byte pieces (whole cache lines) instead
@@ -457,7 +464,7 @@ struct DownWave {
   bool writer, border, two;
   uint32_t rec;                                        // bytes per pair record
   uint32_t vx, vf0, vf1, vpx, vpf0, vpf1, vcj, vpcj;  // lane byte offsets
-  uint32_t vrun;                                       // record offset of lane 1's coarse column
+  uint32_t vrun;                                       // record offset of the first writer lane's coarse column
   uint32_t vspan;                                      // record offset of lane 0's fine column x0
   uint32_t *slice;                                     // this wave's LDS staging slice
   const float *gf;
@@ -1222,8 +1229,8 @@ inline int pick_segment(const Level &cl, int C, long target, int sw) {
 inline long geom_waves(const Geom &g) { return (long)g.nstrips * g.nsegs * g.C; }
 
 // Levels l >= 1 of a job whose level l holds at least this many samples (all
-// channels), with records the fused pass can hold (fusable), run the fused form: down(l) finishes L_l[O] and up(l) is the
-// one-plane collapse.  Smaller levels are latency-bound: there the two extra
+// channels), with records the fused pass can hold (fusable), run the fused
+// form: down(l) finishes L_l[O] and up(l) is the one-plane collapse.  Smaller levels are latency-bound: there the two extra
 // coarse halo rows of every fused down wave cost more than the collapse saves,
 // and they keep the separate form (down(l) stores A_l, up(l) does the EXPAND
 // products and the collapse).  A property of the job alone, so that a job's
