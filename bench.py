@@ -415,7 +415,7 @@ def main():
         print(kernel_source_digest())
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: the filter runs on one GPU; there is no multi-GPU path to measure "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

@@ -45,7 +45,7 @@ typedef enum {
   FLLF_EINVAL = -1,       /* a parameter is out of range or a pointer is NULL */
   FLLF_ENOMEM = -2,       /* the workspace passed is smaller than required */
   FLLF_EDEVICE = -3,      /* a HIP runtime call failed (also reports earlier async faults) */
-  FLLF_EUNSUPPORTED = -4  /* valid request this build does not implement */
+  FLLF_EUNSUPPORTED = -4  /* valid request the library does not implement */
 } fllf_status;
 
 /* Storage of the 2K cosine/sine Gaussian Fourier pyramid levels in the
