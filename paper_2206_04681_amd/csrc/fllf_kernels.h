@@ -361,6 +361,7 @@ struct DownArgs {
   uint32_t *csc; size_t csc_cs;          // level-(l+1) pair records
   float *mc;                             // level-(l+1) boost plane or null
   float *af; size_t af_cs;               // A_l (l >= 1), stored in the O_l slot
+  int minus_g;                           // fused level 1: store L_1[O] - G_1 (see UpArgs::oc_minus_g)
   Geom g;
   Coefs cf;
 };
@@ -373,6 +374,7 @@ struct UpArgs {
   const float *oc; size_t oc_cs;         // O_{l+1} (null when l+1 is the top level)
   const uint32_t *csc; size_t csc_cs;    // level-(l+1) pair records
   float *out; size_t out_cs;             // O_l (the caller's output at level 0)
+  int oc_minus_g;                        // oc holds O_{l+1} - G_{l+1}: G_{l+1} is not read
   Geom g;
   Coefs cf;
 };
@@ -611,8 +613,11 @@ struct DownWave {
           h1.next();
         }
       }
-      A0 = fmaf(-m0, acc0, d.g0);
-      A1 = fmaf(-m1, acc1, d.g1);
+      // with minus_g (fused level 1) the pass leaves L_1[O] - G_1, whose collapse
+      // is the O_1 - G_1 that up(0) expands: it then need not read G_1
+      const float b0 = FUSE && a.minus_g ? 0.f : d.g0, b1 = FUSE && a.minus_g ? 0.f : d.g1;
+      A0 = fmaf(-m0, acc0, b0);
+      A1 = fmaf(-m1, acc1, b1);
       if (!FUSE && writer) {  // this lane owns fine columns x0, x0+1
         const Plane ap(a.af + (size_t)c * a.af_cs);
         const uint32_t so = (uint32_t)r * (uint32_t)a.g.pf * 4u;
@@ -976,7 +981,7 @@ struct UpWave {
     const uint32_t ci = (uint32_t)cfold(i, a.g.Hc, a.g.Hf) * (uint32_t)a.g.pc;
     if (HASD) {
       d.o = Plane(oc).ld1(vcj, ci * 4u);
-      d.g = Plane(gc).ld1(vcj, ci * 4u);
+      d.g = a.oc_minus_g ? 0.f : Plane(gc).ld1(vcj, ci * 4u);  // wave-uniform
     }
     if (SPAN && !BORDER) ld_span<NR>(Plane(csc), ci * rec + vspan, lane, d.q);  // transposed before use
     else ld_record<NR, EX>(Plane(csc), opaque(vpcj), ci * rec, nr, d.q);
@@ -1287,6 +1292,7 @@ inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const
   a.mc = M(l + 1);
   a.af = l == 0 ? nullptr : (float *)(ws + lv[l].off_o);
   a.af_cs = lv[l].g_cstride;
+  a.minus_g = l == 1 && fused_level(P, 1) && L > 2 ? 1 : 0;
   a.g = pass_geom(P, l, true, tu);
   a.cf = P.coefs;
   return a;
@@ -1311,6 +1317,8 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
   a.csc_cs = lv[l + 1].cs_cstride * dwp;
   a.out = l == 0 ? P.out : (float *)(ws + lv[l].off_o);
   a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  // the normal sequence leaves O_1 - G_1 in the O_1 slot when level 1 is fused
+  a.oc_minus_g = l == 0 && hasd && !reparam && fused_level(P, 1) ? 1 : 0;
   a.g = pass_geom(P, l, false, tu, reparam);
   a.cf = P.coefs;
   return a;
@@ -1324,13 +1332,14 @@ inline double down_bytes(const JobPlan &P, int l, int dwp) {
   return C * ((4.0 + pb + 4.0) * lv[l].n + (4.0 + pb) * lv[l + 1].n) + mapb * (lv[l].n + lv[l + 1].n);
 }
 
-inline double up_bytes(const JobPlan &P, int l, int dwp) {
+inline double up_bytes(const JobPlan &P, int l, int dwp, bool reparam = false) {
   const Level *lv = P.lv;
   const double pb = 4.0 * dwp * P.K, C = P.C, mapb = P.m_map ? 4.0 : 0.0;
   const bool hasd = l + 1 < P.levels - 1;
-  if (fused_level(P, l)) return C * (8.0 * lv[l].n + 4.0 * lv[l + 1].n);  // L_l, O_l; O_{l+1} (or G_{l+1})
-  const double fine = l == 0 ? 4.0 : 8.0;               // I, or A_l and G_l
-  const double coarse = 4.0 + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
+  if (!reparam && fused_level(P, l)) return C * (8.0 * lv[l].n + 4.0 * lv[l + 1].n);  // L_l, O_l; O_{l+1}
+  const bool minus_g = l == 0 && hasd && !reparam && fused_level(P, 1);  // O_1 - G_1 in one plane
+  const double fine = l == 0 ? 4.0 : 8.0;                                  // I, or A_l and G_l
+  const double coarse = (minus_g ? 0.0 : 4.0) + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
   return C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n) + mapb * lv[l].n;  // + O_l written
 }
 
@@ -1442,7 +1451,7 @@ hipError_t launch_reparam_typed(const JobPlan &P, char *ws, hipStream_t st, Laun
       if (hasd) up_kernel<ST, KM, true, false, false, true, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
       else up_kernel<ST, KM, true, false, false, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
     }
-    if (hook) hook->after(st, kUpNames[l], up_bytes(P, l, dwp));
+    if (hook) hook->after(st, kUpNames[l], up_bytes(P, l, dwp, true));
   }
   return hipGetLastError();
 }
