@@ -94,8 +94,10 @@ void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning 
     bool ex;
     k_class(it.P->K, &km, &ex);
     const bool hasd = !it.down && it.l + 1 < it.P->levels - 1;
-    const bool fuse = fused_level(*it.P, it.l);
-    if (!it.down && fuse)  // the collapse: one kernel for every job
+    if (!it.down && it.l == 1 && fold_level1(*it.P)) continue;  // done inside up(0)
+    // fused level l; for up(0), whether the level-1 collapse is folded in
+    const bool fuse = !it.down && it.l == 0 ? fold_level1(*it.P) : fused_level(*it.P, it.l);
+    if (!it.down && it.l >= 1 && fuse)  // the collapse: one kernel for every job
       groups[Key(1, false, 0, false, false, false, true)].push_back(i);
     else
       groups[Key(it.down ? 0 : 1, it.l == 0, km, ex, it.P->m_map != nullptr, hasd, fuse)].push_back(i);
@@ -129,7 +131,7 @@ void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning 
           std::memcpy(out->blob.data() + b.args_off + rec * q, &a, rec);
         } else {
           UpArgs a = make_up_args(*it.P, it.l, ws, dwp, tu);
-          if (b.fuse && !a.oc) a.oc = a.gc;  // the collapse expands G_{l+1} at the top
+          if (b.fuse && !b.l0 && !a.oc) a.oc = a.gc;  // the collapse expands G_{l+1} at the top
           std::memcpy(out->blob.data() + b.args_off + rec * q, &a, rec);
         }
       }
@@ -176,8 +178,9 @@ void build_batch(const JobPlan *P, int n, fllf_storage storage, char *ws, const 
 size_t step_table_bound(int n) {
   // per launch group: the records and n_g + 1 offsets, each padded to kAlign;
   // groups: down 6 K loops x 2 maps x (level 0, separate, fused) = 36, up
-  // 6 x 2 x 2 top flags x (level 0, separate) = 48, and the collapse
-  const size_t groups = 85;
+  // 6 x 2 x 2 top flags x (level 0, separate) = 48, up(0) with the level-1
+  // collapse folded in 6 x 2 = 12, and the collapse
+  const size_t groups = 97;
   const size_t rec = std::max(sizeof(DownArgs), sizeof(UpArgs));
   return align_up(rec * (size_t)n + 4 * (size_t)n + groups * (4 + 2 * (kAlign - 1)));
 }

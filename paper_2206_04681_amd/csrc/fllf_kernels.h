@@ -375,6 +375,10 @@ struct UpArgs {
   const uint32_t *csc; size_t csc_cs;    // level-(l+1) pair records
   float *out; size_t out_cs;             // O_l (the caller's output at level 0)
   int oc_minus_g;                        // oc holds O_{l+1} - G_{l+1}: G_{l+1} is not read
+  // up(0) with the level-1 collapse folded in: oc holds L_1[O] - G_1 and the pass
+  // adds EXPAND(O_2) itself; o2 is O_2 (G_2 when level 2 is the top), w2 x h2, pitch p2
+  const float *o2; size_t o2_cs;
+  int w2, h2, p2;
   Geom g;
   Coefs cf;
 };
@@ -918,13 +922,18 @@ collapse_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restric
 
 // RW: re-parameterisation; the resident records carry the previous alpha~_k
 // and every term is reweighted by wt[k] (new / previous alpha~_k).
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false>
+// FOLD (level 0 only): the collapse of level 1 is done here, on the fly:
+// O_1 - G_1 = (L_1[O] - G_1) + EXPAND(O_2) at every level-1 sample the pass reads.
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false, bool FOLD = false>
 struct UpWave {
+  static_assert(!FOLD || (L0 && HASD && !RW), "the level-1 collapse folds into up(0) only");
   using PS = PairStore<ST>;
   static constexpr int DW = PS::DW;
   static constexpr int NR = KM * DW;
   struct CRow {  // coarse row as loaded (raw): O_{l+1}, G_{l+1}, pair record, at column cj
     float o, g;
+    float e[FOLD ? 9 : 1];  // FOLD: O_2 at rows p-1..p+1 x columns q-1..q+1 around (ci, cj)
+    int par;                // FOLD: parity of the level-1 row ci
     uint32_t q[NR];
   };
   struct FBlk {  // fine 2x2 block as loaded: G (or I), A (or I), boost
@@ -942,6 +951,9 @@ struct UpWave {
   const float *gc, *oc, *base, *gfp;
   const uint32_t *csc;
   float *outp;
+  const float *o2p;   // FOLD: O_2 of this channel
+  uint32_t vq[3];     // FOLD: byte offsets of the level-2 columns q-1, q, q+1 (folded)
+  float wx[3];        // FOLD: their EXPAND weights at the lane's level-1 column
 
   __device__ UpWave(const UpArgs &args, int lane_, int c_, int strip, int seg, uint32_t *slice_) : a(args) {
     const Geom &g = a.g;
@@ -974,14 +986,35 @@ struct UpWave {
     oc = HASD ? a.oc + (size_t)c * a.oc_cs : nullptr;
     csc = a.csc + (size_t)c * a.csc_cs;
     base = a.base + (size_t)c * a.base_cs;
+    if (FOLD) {
+      o2p = a.o2 + (size_t)c * a.o2_cs;
+      const int q = cj >> 1;
+      const bool odd = cj & 1;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) vq[d] = (uint32_t)cfold(q + d - 1, a.w2, g.Wc) * 4u;
+      wx[0] = odd ? 0.f : 0.125f;
+      wx[1] = odd ? 0.5f : 0.75f;
+      wx[2] = odd ? 0.5f : 0.125f;
+    }
   }
 
   template <bool BORDER>
   __device__ inline void load_c(CRow &d, int i) const {
-    const uint32_t ci = (uint32_t)cfold(i, a.g.Hc, a.g.Hf) * (uint32_t)a.g.pc;
+    const int cr = cfold(i, a.g.Hc, a.g.Hf);
+    const uint32_t ci = (uint32_t)cr * (uint32_t)a.g.pc;
     if (HASD) {
       d.o = Plane(oc).ld1(vcj, ci * 4u);
       d.g = a.oc_minus_g ? 0.f : Plane(gc).ld1(vcj, ci * 4u);  // wave-uniform
+    }
+    if (FOLD) {  // the 3 x 3 level-2 neighbourhood that EXPAND takes to (cr, cj)
+      d.par = cr & 1;
+      const Plane p2(o2p);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const uint32_t ro = (uint32_t)cfold((cr >> 1) + dy - 1, a.h2, a.g.Hc) * (uint32_t)a.p2 * 4u;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) d.e[3 * dy + dx] = p2.ld1(vq[dx], ro);
+      }
     }
     if (SPAN && !BORDER) ld_span<NR>(Plane(csc), ci * rec + vspan, lane, d.q);  // transposed before use
     else ld_record<NR, EX>(Plane(csc), opaque(vpcj), ci * rec, nr, d.q);
@@ -990,6 +1023,18 @@ struct UpWave {
   template <bool BORDER>
   __device__ inline void ready(CRow &d) {
     if (SPAN && !BORDER) transpose_span<NR>(d.q, slice, lane);
+  }
+
+  // O_{l+1} - G_{l+1} at a coarse sample (FOLD: the level-1 collapse, on the fly;
+  // EXPAND weights (1 6 1)/8 at even and (0 4 4)/8 at odd level-1 positions)
+  __device__ inline float dval(const CRow &d) const {
+    if (!FOLD) return d.o - d.g;
+    const float w0 = d.par ? 0.f : 0.125f, w1 = d.par ? 0.5f : 0.75f, w2 = d.par ? 0.5f : 0.125f;
+    float h[3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+      h[dy] = fmaf(wx[0], d.e[3 * dy], fmaf(wx[1], d.e[3 * dy + 1], wx[2] * d.e[3 * dy + 2]));
+    return d.o + fmaf(w0, h[0], fmaf(w1, h[1], w2 * h[2]));
   }
 
   // pair k of a coarse record as float32 (reweighted when re-parameterising)
@@ -1046,12 +1091,12 @@ struct UpWave {
       load_c<BORDER>(rp, i0 + 1);
       load_f<BORDER>(fa, i0);
       ready<BORDER>(t0);
-      if (HASD) Dm = t0.o - t0.g;
+      if (HASD) Dm = dval(t0);
 #pragma unroll
       for (int k = 0; k < KM; ++k)
         if (EX || k < K) { const float2 v = term(t0.q, k); Cm[k] = v.x; Sm[k] = v.y; }
       ready<BORDER>(t1);
-      if (HASD) D0 = t1.o - t1.g;
+      if (HASD) D0 = dval(t1);
 #pragma unroll
       for (int k = 0; k < KM; ++k)
         if (EX || k < K) { const float2 v = term(t1.q, k); C0[k] = v.x; S0[k] = v.y; }
@@ -1061,7 +1106,7 @@ struct UpWave {
       load_c<BORDER>(rn, i + 2);
       ready<BORDER>(rp);
       load_f<BORDER>(fb, i + 1 < i1 ? i + 1 : i);
-      const float Dp = HASD ? rp.o - rp.g : 0.f;
+      const float Dp = HASD ? dval(rp) : 0.f;
       float ED[4] = {0.f, 0.f, 0.f, 0.f};
       if (HASD) expand4(Dm, D0, Dp, ED);
       Harmonics hm[4];
@@ -1128,9 +1173,9 @@ struct UpWave {
   }
 };
 
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false>
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false, bool FOLD = false>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs a) {
-  using W = UpWave<ST, KM, EX, L0, MAP, HASD, RW>;
+  using W = UpWave<ST, KM, EX, L0, MAP, HASD, RW, FOLD>;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * W::SLICE];
   int lane, strip, seg, c;
   if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
@@ -1138,10 +1183,10 @@ __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs 
   w.run();
 }
 
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD>
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool FOLD = false>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM))
 up_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n, uint32_t total) {
-  using W = UpWave<ST, KM, EX, L0, MAP, HASD>;
+  using W = UpWave<ST, KM, EX, L0, MAP, HASD, false, FOLD>;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * W::SLICE];
   const int lane = threadIdx.x & 63;
   const uint32_t stride = gridDim.x * 4u;
@@ -1245,6 +1290,11 @@ inline bool fused_level(const JobPlan &P, int l) {
   return l >= 1 && fusable(P.K, P.dwp) && (double)P.lv[l].n * P.C >= kFuseMinSamples;
 }
 
+// A fused level 1 below the top has its collapse folded into up(0), which then
+// reads L_1[O] - G_1 and O_2 instead of O_1 - G_1 (one level-1 plane less to
+// write and read, and one launch less).
+inline bool fold_level1(const JobPlan &P) { return P.levels > 2 && fused_level(P, 1); }
+
 // Geometry of pass down(l) / up(l) of a job: coarse columns per strip (the
 // fused down(l) uses strips of 60) and the tuned segment length.  The up passes
 // that evaluate the product-sum (level 0, levels that are not fused, and every
@@ -1317,8 +1367,16 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
   a.csc_cs = lv[l + 1].cs_cstride * dwp;
   a.out = l == 0 ? P.out : (float *)(ws + lv[l].off_o);
   a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
-  // the normal sequence leaves O_1 - G_1 in the O_1 slot when level 1 is fused
+  // the normal sequence leaves L_1[O] - G_1 in the O_1 slot when level 1 is
+  // fused; up(0) adds EXPAND(O_2) itself
   a.oc_minus_g = l == 0 && hasd && !reparam && fused_level(P, 1) ? 1 : 0;
+  if (a.oc_minus_g) {
+    a.o2 = (const float *)(ws + (2 < L - 1 ? lv[2].off_o : lv[2].off_g));
+    a.o2_cs = lv[2].g_cstride;
+    a.w2 = lv[2].w;
+    a.h2 = lv[2].h;
+    a.p2 = lv[2].pitch;
+  }
   a.g = pass_geom(P, l, false, tu, reparam);
   a.cf = P.coefs;
   return a;
@@ -1337,10 +1395,11 @@ inline double up_bytes(const JobPlan &P, int l, int dwp, bool reparam = false) {
   const double pb = 4.0 * dwp * P.K, C = P.C, mapb = P.m_map ? 4.0 : 0.0;
   const bool hasd = l + 1 < P.levels - 1;
   if (!reparam && fused_level(P, l)) return C * (8.0 * lv[l].n + 4.0 * lv[l + 1].n);  // L_l, O_l; O_{l+1}
-  const bool minus_g = l == 0 && hasd && !reparam && fused_level(P, 1);  // O_1 - G_1 in one plane
-  const double fine = l == 0 ? 4.0 : 8.0;                                  // I, or A_l and G_l
-  const double coarse = (minus_g ? 0.0 : 4.0) + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
-  return C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n) + mapb * lv[l].n;  // + O_l written
+  const bool fold = l == 0 && hasd && !reparam && fused_level(P, 1);  // L_1[O] - G_1, and O_2
+  const double fine = l == 0 ? 4.0 : 8.0;                               // I, or A_l and G_l
+  const double coarse = (fold ? 0.0 : 4.0) + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
+  const double o2 = fold ? 4.0 * lv[2].n : 0.0;
+  return C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n + o2) + mapb * lv[l].n;  // + O_l written
 }
 
 // The fused down pass exists for the fusable K loops only (fused_level never
@@ -1349,6 +1408,14 @@ template <int ST, int KM, bool EX, bool MAP>
 void launch_fused_down(const DownArgs &a, hipStream_t st) {
   if constexpr (EX && fusable(KM, PairStore<ST>::DW))
     down_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+}
+
+// up(0) with the level-1 collapse folded in: exists for the fusable K loops only
+// (fold_level1 implies a fused level 1).
+template <int ST, int KM, bool EX, bool MAP>
+void launch_fold_up(const UpArgs &a, hipStream_t st) {
+  if constexpr (EX && fusable(KM, PairStore<ST>::DW))
+    up_kernel<ST, KM, EX, true, MAP, true, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
 }
 
 template <int ST, int KM, bool EX, bool MAP>
@@ -1366,6 +1433,7 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
     post(kDownNames[l], down_bytes(P, l, dwp));
   }
   for (int l = L - 2; l >= 0; --l) {
+    if (l == 1 && fold_level1(P)) continue;  // done inside up(0)
     const UpArgs a = make_up_args(P, l, ws, dwp, tu);
     const bool hasd = a.oc != nullptr;
     pre();
@@ -1374,7 +1442,8 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
       if (!hasd) ca.oc = ca.gc;  // O_{l+1} is G_{l+1} at the top
       collapse_kernel<ST><<<grid_for(ca.g), block_for(ca.g), 0, st>>>(ca);
     } else if (l == 0) {
-      if (hasd) up_kernel<ST, KM, EX, true, MAP, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+      if (a.o2) launch_fold_up<ST, KM, EX, MAP>(a, st);
+      else if (hasd) up_kernel<ST, KM, EX, true, MAP, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
       else up_kernel<ST, KM, EX, true, MAP, false><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
     } else {
       if (hasd) up_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
@@ -1508,16 +1577,23 @@ hipError_t launch_batch_typed(const BatchLaunch &b, char *ws, hipStream_t st, co
 #undef FLLF_DOWN
   } else {
     const UpArgs *args = (const UpArgs *)(ws + b.args_off);
-#define FLLF_UP(L0, HASD)                                                               \
+#define FLLF_UP(L0, HASD, FOLD)                                                         \
   {                                                                                     \
-    auto k = up_batch_kernel<ST, KM, EX, L0, MAP, HASD>;                                \
+    auto k = up_batch_kernel<ST, KM, EX, L0, MAP, HASD, FOLD>;                          \
     k<<<batch_grid(b, (const void *)k, tu), blk, 0, st>>>(args, start, b.njobs, b.waves); \
   }
-    // the product-sum and collapse (fused levels run collapse_batch_kernel)
+    // the product-sum and collapse (fused levels run collapse_batch_kernel); at
+    // level 0, fuse marks the jobs whose level-1 collapse is folded in
     if (b.l0) {
-      if (b.hasd) FLLF_UP(true, true) else FLLF_UP(true, false)
+      if (b.fuse) {
+        if constexpr (EX && fusable(KM, PairStore<ST>::DW)) FLLF_UP(true, true, true)
+      } else if (b.hasd) {
+        FLLF_UP(true, true, false)
+      } else {
+        FLLF_UP(true, false, false)
+      }
     } else {
-      if (b.hasd) FLLF_UP(false, true) else FLLF_UP(false, false)
+      if (b.hasd) FLLF_UP(false, true, false) else FLLF_UP(false, false, false)
     }
 #undef FLLF_UP
   }
@@ -1532,7 +1608,7 @@ hipError_t launch_batch_storage(const BatchSchedule &s, char *ws, hipStream_t st
     hipError_t e = hipSuccess;
     if (b.kind == 2) {
       e = hipMemcpyAsync(b.copy_dst, b.copy_src, b.copy_bytes, hipMemcpyDeviceToDevice, st);
-    } else if (b.kind == 1 && b.fuse) {  // the collapse does not depend on K
+    } else if (b.kind == 1 && b.fuse && !b.l0) {  // the collapse does not depend on K
       const UpArgs *args = (const UpArgs *)(ws + b.args_off);
       const uint32_t *start = (const uint32_t *)(ws + b.start_off);
       auto k = collapse_batch_kernel<ST>;
