@@ -176,3 +176,14 @@ def test_input_inside_the_workspace_is_rejected(torch_dev):
     assert e.value.status == fllf.FLLF_EINVAL and "input overlaps" in str(e.value)
     torch.cuda.synchronize()
     assert bool((out == -3.0).all())
+
+
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_fused_level1_shallow_pyramids(torch_dev, L):
+    """1500x1100 RGB: level 1 takes the fused form.  With 3 levels, level 2 is
+    the top and up(0) folds in the collapse from G_2; with 2 levels, level 1
+    is the top and nothing is fused."""
+    img = _img(1100, 1500, c=3, seed=40 + L)
+    got = gpu_run(torch_dev, img, L, 0.15, 2.5, 8)
+    want = ref.fourier_llf(img[0].astype(np.float64), L, 0.15, 2.5, 8)
+    assert ref.max_abs(got[0], want) <= TOL_F32
