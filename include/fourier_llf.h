@@ -130,8 +130,9 @@ fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_
  *     waves a pass aims for when it splits its rows into segments (more waves =
  *     shorter segments = more halo rows re-read): the REDUCE pass from level 0;
  *     from levels >= 1; the up passes that evaluate the product-sum of Eq. (14)
- *     (to level 0, to levels below 2^20 samples, and all re-parameterised
- *     passes); and the one-plane collapse to the larger levels >= 1;
+ *     (to level 0 and to levels below 2^20 samples; re-parameterised passes
+ *     use a built-in target); and the one-plane collapse to the larger levels
+ *     >= 1;
  *   FLLF_TUNE_GRID_CAP: 0 = a batched launch has one wave per work item; c > 0
  *     = at most c times the blocks resident on the device at once, each wave
  *     looping over work items (persistent launch). */

@@ -34,19 +34,13 @@ const char *const kBatchUpNames[kMaxLevels] = {
     "bup_l8", "bup_l9", "bup_l10", "bup_l11", "bup_l12", "bup_l13", "bup_l14", "bup_l15"};
 
 Tuning default_tuning(fllf_storage storage) {
-  // Autotuned on the 3840x2160 RGB K = 8 workload.  The level-0 passes read
-  // little per fine row and want many short segments; the float32 passes
-  // that read a level of records (one wave per SIMD) want long ones.
+  // Autotuned on the 3840x2160 RGB K = 8 workload.  The level-0 passes want
+  // many short segments; the float32 down passes that read a level of records
+  // (one wave per SIMD) want long ones.
   Tuning t;
-  if (storage == FLLF_STORE_F32) {
-    t.p[kTuneDown0] = 12288;
-    t.p[kTuneDown] = 512;
-    t.p[kTuneUp0] = 1536;  // as fast as 8-row segments, without re-reading a quarter of the records
-  } else {
-    t.p[kTuneDown0] = 12288;
-    t.p[kTuneDown] = 1536;
-    t.p[kTuneUp0] = 12288;
-  }
+  t.p[kTuneDown0] = 12288;
+  t.p[kTuneDown] = storage == FLLF_STORE_F32 ? 512 : 1536;
+  t.p[kTuneUp0] = 12288;  // up(0) with the level-1 collapse folded in wants short segments
   // up(l >= 1) is the one-plane collapse on the large levels: little work per
   // row, so short segments (many waves) hide the row latency
   t.p[kTuneUp] = 12288;

@@ -1295,16 +1295,21 @@ inline bool fused_level(const JobPlan &P, int l) {
 // write and read, and one launch less).
 inline bool fold_level1(const JobPlan &P) { return P.levels > 2 && fused_level(P, 1); }
 
+// Segment target of the re-parameterised up passes: they evaluate the whole
+// product-sum at every level from the resident records, which wants long
+// segments (the autotuner times normal runs only, so this one is built in).
+constexpr long kReparamUpWaves = 1536;
+
 // Geometry of pass down(l) / up(l) of a job: coarse columns per strip (the
 // fused down(l) uses strips of 60) and the tuned segment length.  The up passes
-// that evaluate the product-sum (level 0, levels that are not fused, and every
-// re-parameterised pass) share one segment target; the one-plane collapse of
-// the fused levels has its own.
+// that evaluate the product-sum (level 0 and levels that are not fused) share
+// one segment target; the one-plane collapse of the fused levels has its own.
 inline Geom pass_geom(const JobPlan &P, int l, bool down, const Tuning &tu, bool reparam = false) {
   const bool collapse = !down && !reparam && fused_level(P, l);
   const int kind = down ? (l == 0 ? kTuneDown0 : kTuneDown) : (collapse ? kTuneUp : kTuneUp0);
+  const long target = !down && reparam ? kReparamUpWaves : (long)tu.p[kind];
   const int sw = down && fused_level(P, l) ? 60 : 62;
-  return make_geom(P.lv[l], P.lv[l + 1], P.C, pick_segment(P.lv[l + 1], P.C, tu.p[kind], sw), sw);
+  return make_geom(P.lv[l], P.lv[l + 1], P.C, pick_segment(P.lv[l + 1], P.C, target, sw), sw);
 }
 
 // Launch shape of a single-job pass: blocks of four waves, or of one wave when

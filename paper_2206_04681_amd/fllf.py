@@ -34,8 +34,9 @@ EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run
             "fourier_llf_reparam")
 
 # Launch-shape parameters (FLLF_TUNE_*): target waves of the REDUCE pass from
-# level 0 and from levels >= 1, of the up passes that evaluate the product-sum,
-# and of the one-plane collapse of the fused levels; then the grid cap.
+# level 0 and from levels >= 1, of the up passes that evaluate the product-sum
+# (not the re-parameterised ones), and of the one-plane collapse of the fused
+# levels; then the grid cap.
 TUNE_NAMES = ("down0", "down", "up0", "up", "grid_cap")
 
 
