@@ -202,3 +202,21 @@ def test_batch_with_one_invalid_job_launches_nothing(torch_dev):
     torch.cuda.synchronize()
     for o in outs:
         assert bool((o == -5.0).all())
+
+
+def test_batch_with_fused_jobs_and_a_boost_map(torch_dev):
+    """Jobs large enough for the fused levels (one of them with a boost map and
+    its level-1 collapse folded into up(0)) batched with small ones: every
+    batched result equals its single-job run bit for bit."""
+    torch = torch_dev
+    specs = [((1, 2200, 2000), 7, 0.2, 2.0, 8, True),   # fused levels 1-2, boost map
+             ((3, 1100, 1500), 3, 0.12, 2.0, 8, False),  # fused level 1, level 2 the top
+             ((3, 1100, 1500), 6, 0.1, 3.0, 4, False),
+             ((1, 90, 70), 5, 0.2, 0.0, 6, True),
+             ((3, 64, 99), 5, 0.1, 3.0, 8, False)]
+    ctx = _ctx()
+    jobs, fjobs, outs = _mixed_jobs(torch, ctx, specs=specs, seed=120)
+    ctx.run_jobs(fjobs)
+    torch.cuda.synchronize()
+    for i, (j, o) in enumerate(zip(jobs, outs)):
+        assert torch.equal(_alone(torch, ctx, j), o), i
