@@ -55,7 +55,24 @@ def build(verbose: bool = False) -> str:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
     os.replace(tmp_lib, LIB)
+    build_c_client(cc, verbose)
     return LIB
+
+
+# A host program that calls the library through its C interface only (tests).
+C_CLIENT_SRC = os.path.join(ROOT, "tests", "c_client.cpp")
+C_CLIENT = os.path.join(ROOT, "tests", "c_client")
+
+
+def build_c_client(cc: str, verbose: bool = False) -> str:
+    tmp = C_CLIENT + ".tmp"
+    cmd = [cc, "-std=c++17", "-O2", f"--offload-arch={ARCH}", "-I", INCLUDE] + DEVICE_FLAGS + [
+        C_CLIENT_SRC, "-L", HERE, "-lfourier_llf", "-Wl,-rpath,$ORIGIN/../paper_2206_04681_amd", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, C_CLIENT)
+    return C_CLIENT
 
 
 if __name__ == "__main__":
