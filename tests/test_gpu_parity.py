@@ -187,3 +187,15 @@ def test_fused_level1_shallow_pyramids(torch_dev, L):
     got = gpu_run(torch_dev, img, L, 0.15, 2.5, 8)
     want = ref.fourier_llf(img[0].astype(np.float64), L, 0.15, 2.5, 8)
     assert ref.max_abs(got[0], want) <= TOL_F32
+
+
+@pytest.mark.parametrize("h,w", [(65536, 4), (4, 65536)])
+def test_fused_levels_on_thin_images(torch_dev, h, w):
+    """16 channels, 4 samples across at the 65536-sample side limit: level 1 is
+    2 wide with exactly 2^20 samples over the channels (so fused) and level 2
+    one sample: the fused level-1 pass with one strip or over a thousand, the
+    folded collapse reading a one-sample level 2.  Channel 0 against the oracle."""
+    img = _img(h, w, c=16, seed=h % 97 + w % 89)
+    got = gpu_run(torch_dev, img, 3, 0.2, 2.0, 4)
+    want = ref.fourier_llf(img[0].astype(np.float64), 3, 0.2, 2.0, 4)
+    assert ref.max_abs(got[0], want) <= TOL_F32
