@@ -93,3 +93,21 @@ def test_fused_levels_odd_sizes_against_oracle(odd_rgb, storage, K, use_map):
     assert err <= tol
     if min_psnr is not None:
         assert p >= min_psnr
+
+
+def test_large_image_zero_boost_is_identity():
+    """11000 x 11000 gray, 8 levels, K=8, float32 pyramids (level-1 records
+    1.9 GB, below the 4 GiB plane limit; fused levels 1-3, folded collapse):
+    with m = 0 the filter returns its input up to rounding, a property that
+    holds at any size, checked here where the plane offsets pass 2^30."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2206_04681_amd.fllf import FourierLLF
+    img = synth_image(11000, 11000, 1, seed=23, n_rect=30, n_disk=30, noise=0.01)
+    x = torch.from_numpy(img).cuda()
+    print("\n11000x11000 gray, m = 0", flush=True)
+    out = FourierLLF("f32").run(x, 8, 0.1, 0.0, 8)
+    torch.cuda.synchronize()
+    err = float((out - x).abs().max())
+    print(f"max |out - in| = {err:.3e}", flush=True)
+    assert err <= 1e-5
