@@ -254,7 +254,9 @@ void fourier_llf_server_destroy(fllf_server *srv);
  * timing was enabled (or last read). */
 typedef struct {
   char name[32];      /* kernel class: "down_l<l>" (REDUCE from level l), "up_l<l>"
-                         (product-sum and collapse at level l), "bdown_l<l>" / "bup_l<l>"
+                         (product-sum and collapse at level l; a job whose level 1 is
+                         large enough for the fused form has no "up_l1": its level-1
+                         collapse runs inside "up_l0"), "bdown_l<l>" / "bup_l<l>"
                          (batched launches), "half_l<l>" (re-parameterisation), "copy" */
   int32_t launches;   /* number of launches */
   double total_ms;    /* summed hipEvent durations */
