@@ -220,3 +220,24 @@ def test_batch_with_fused_jobs_and_a_boost_map(torch_dev):
     torch.cuda.synchronize()
     for i, (j, o) in enumerate(zip(jobs, outs)):
         assert torch.equal(_alone(torch, ctx, j), o), i
+
+
+def test_results_do_not_depend_on_the_launch_shape(torch_dev):
+    """Segment lengths and block shapes change which wave computes which row,
+    never the arithmetic of a sample: two very different tunings give the same
+    outputs bit for bit (small jobs and fused-size ones, batched)."""
+    torch = torch_dev
+    specs = MIXED + [((3, 1100, 1500), 6, 0.12, 2.0, 8, False), ((1, 1300, 1700), 7, 0.2, 2.0, 8, True)]
+    ctx = _ctx()
+    jobs, fjobs, outs = _mixed_jobs(torch, ctx, specs=specs, seed=140)
+    ctx.run_jobs(fjobs)
+    torch.cuda.synchronize()
+    first = [o.clone() for o in outs]
+    for o in outs:
+        o.fill_(-3.0)
+    ctx.set_tuning([512, 24576, 512, 512, 0])
+    ctx.run_jobs(fjobs)
+    torch.cuda.synchronize()
+    ctx.set_tuning(None)
+    for i, (a, b) in enumerate(zip(first, outs)):
+        assert torch.equal(a, b), i
