@@ -18,6 +18,7 @@
 // A serving step uses the same launches for independent passes of different
 // jobs: passes of one kernel class share a launch whatever their level.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -61,7 +62,15 @@ uint32_t pass_waves(const JobPlan &P, int l, bool down, const Tuning &tu) {
 // the given (job, pass) items.  Items of one class may be at different levels:
 // down(l >= 1) passes of any level share a kernel, as do up(l >= 1) passes, and
 // the collapses of all fused levels share one launch.
-void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning &tu, BatchSchedule *out) {
+void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning &tu0, BatchSchedule *out) {
+  // n jobs share each launch of the pass, so every job aims at fewer waves
+  // (longer segments, less halo): the targets of the level-0 passes and of the
+  // collapse scale with 1/sqrt(n).  Results do not depend on the launch shape.
+  Tuning tu = tu0;
+  if (n > 1) {
+    const double f = 1.0 / std::sqrt((double)n);
+    for (int k : {kTuneDown0, kTuneUp0, kTuneUp}) tu.p[k] = std::max(256, (int)(tu0.p[k] * f));
+  }
   size_t off = out->blob.size();
   auto reserve = [&](size_t bytes) {
     const size_t at = off;
