@@ -68,7 +68,8 @@ def odd_rgb():
 
 
 @pytest.mark.parametrize("storage,K,use_map", [("f32", 8, False), ("f32", 4, False), ("f32", 8, True),
-                                               ("f16", 16, False), ("bf16", 8, False)])
+                                               ("f16", 16, False), ("f16", 8, True), ("bf16", 8, False),
+                                               ("bf16", 16, False)])
 def test_fused_levels_odd_sizes_against_oracle(odd_rgb, storage, K, use_map):
     torch, img, x = odd_rgb
     from paper_2206_04681_amd.fllf import FourierLLF
