@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import fourier_llf_ref as ref
+from oracle_pool import oracle_channels, report
 from paper_2206_04681_amd.synth import batch_workloads, synth_image
 
 pytestmark = pytest.mark.gpu
@@ -167,7 +168,8 @@ def test_autotune_keeps_results(torch_dev):
 
 def test_uneven_batch_of_64_full_size(torch_dev):
     """The 64-image uneven batch at full size: batched == single-job runs for every
-    image, and the two smallest images against the oracle."""
+    image; the two smallest images, and every channel of the largest RGB image
+    (fused levels in the batched kernels), against the oracle."""
     torch = torch_dev
     from paper_2206_04681_amd.fllf import Job
     ctx = _ctx()
@@ -184,6 +186,11 @@ def test_uneven_batch_of_64_full_size(torch_dev):
         w = ws[i]
         want = ref.fourier_llf_image(xs[i].cpu().numpy().astype(np.float64), w.levels, w.sigma_r, w.m, w.K)
         assert ref.max_abs(prepared[i][1].cpu().numpy(), want) <= TOL_F32, i
+    big = max((i for i in range(len(ws)) if ws[i].channels == 3), key=lambda i: ws[i].height * ws[i].width)
+    w = ws[big]
+    want = oracle_channels(xs[big].cpu().numpy(), w.levels, w.sigma_r, w.m, w.K)
+    errs, _ = report(f"batched {w.width}x{w.height} RGB", prepared[big][1].cpu().numpy(), want)
+    assert max(errs) <= TOL_F32
 
 
 def test_batch_with_one_invalid_job_launches_nothing(torch_dev):
