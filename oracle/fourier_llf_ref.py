@@ -75,6 +75,39 @@ def fit_period(sigma_r: float, K: int, R: float = 1.0) -> float:
     return 0.5 * (a + b)
 
 
+def fit_period_range(sigma_lo: float, sigma_hi: float, K: int, R: float = 1.0) -> float:
+    """One period for every range scale in [sigma_lo, sigma_hi] (pixel-by-pixel
+    alpha~_{k,p}, Sec. III-B, where one T must serve all pixels).  Each term of
+    Eq. (12) is taken at the scale where it is largest: the truncation term
+    erfc(pi sigma (2K+1) / T) grows as sigma falls, the aliasing term
+    erfc((T - R) / sigma) as sigma rises, so
+        T = argmin_{T > R} erfc(pi sigma_lo (2K+1) / T) + erfc((T - R) / sigma_hi).
+    Same plain scan and golden-section search as fit_period; with
+    sigma_lo = sigma_hi it is Eq. (12) itself."""
+    if not (0 < sigma_lo <= sigma_hi) or K < 1 or R <= 0:
+        raise ValueError("0 < sigma_lo <= sigma_hi, K >= 1 and R > 0 are required")
+
+    def E(T):
+        return math.erfc(math.pi * sigma_lo * (2 * K + 1) / T) + math.erfc((T - R) / sigma_hi)
+
+    lo = R
+    hi = R + 20.0 * sigma_hi + 4.0 * math.pi * sigma_lo * (2 * K + 1)
+    n = 20000
+    grid = [lo + (hi - lo) * (i + 1) / n for i in range(n)]
+    i = int(np.argmin([E(t) for t in grid]))
+    a = grid[max(i - 1, 0)] if i > 0 else lo
+    b = grid[min(i + 1, n - 1)]
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    for _ in range(300):
+        c = b - g * (b - a)
+        d = a + g * (b - a)
+        if E(c) < E(d):
+            b = d
+        else:
+            a = c
+    return 0.5 * (a + b)
+
+
 def fourier_coefficients(sigma_r: float, K: int, T: float):
     """omega_k, alpha_k and alpha~_k for k = 1..K (Eq. (9) and Eq. (11)).
 
@@ -236,20 +269,49 @@ def fourier_llf_image(img: np.ndarray, levels: int, sigma_r: float, m: float, K:
     return np.stack([fourier_llf(c, levels, sigma_r, m, K, R, T) for c in img])
 
 
-def fourier_llf_adaptive(I: np.ndarray, levels: int, sigma_r: float, m_map: np.ndarray,
-                         K: int, R: float = 1.0, T: float | None = None) -> np.ndarray:
-    """Pixel-by-pixel Fourier LLF (Sec. III-B): m replaced by m_p per pixel.
+def alpha_tilde_of(sigma, K: int, T: float) -> np.ndarray:
+    """alpha~_k = 2 sigma^2 alpha_k omega_k (Eq. (9), Eq. (11)) for an array of
+    range scales: shape (K,) + sigma.shape, written out from Eq. (9) at each sigma."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    k = np.arange(1, K + 1, dtype=np.float64).reshape((K,) + (1,) * sigma.ndim)
+    omega = 2.0 * math.pi * k / T
+    alpha = sigma * math.sqrt(2.0 * math.pi) / T * np.exp(-0.5 * (omega * sigma) ** 2)
+    return 2.0 * sigma ** 2 * alpha * omega
 
-    m_p is given at level 0 and brought to level l by the Gaussian pyramid
-    (its value at the level-l pixel p).  The Fourier pyramids are unchanged;
-    only the coefficient m at each level-l pixel changes.
+
+def fourier_llf_adaptive(I: np.ndarray, levels: int, sigma_r: float, m_map: np.ndarray | None,
+                         K: int, R: float = 1.0, T: float | None = None,
+                         sigma_map: np.ndarray | None = None, m: float | None = None) -> np.ndarray:
+    """Pixel-by-pixel Fourier LLF (Sec. III-B): alpha~_k replaced by alpha~_{k,p}
+    and/or m by m_p, pixel by pixel, in Eq. (14).
+
+    The maps are given at level 0 and brought to level l by the Gaussian pyramid
+    (their value at the level-l pixel p): sigma_p = G_l[sigma_map]_p gives
+    alpha~_{k,p} through Eq. (9) and (11), m_p = G_l[m_map]_p.  The Fourier
+    pyramids depend on the remap only through omega_k = 2 pi k / T, so they are
+    those of the fixed case; a sigma map therefore needs one T for every pixel
+    (given, or fitted to the map's range by fit_period_range).  Without a map
+    the scalar (sigma_r, or m -- m_map None needs m) is used.
     """
     I = np.asarray(I, dtype=np.float64)
-    if T is None:
+    if sigma_map is not None:
+        sigma_map = np.asarray(sigma_map, dtype=np.float64)
+        if T is None:
+            T = fit_period_range(float(sigma_map.min()), float(sigma_map.max()), K, R)
+    elif T is None:
         T = fit_period(sigma_r, K, R)
-    omega, _, alpha_t, _ = fourier_coefficients(sigma_r, K, T)
+    omega = 2.0 * math.pi * np.arange(1, K + 1) / T
     G = gaussian_pyramid(I, levels)
-    M = gaussian_pyramid(np.asarray(m_map, dtype=np.float64), levels)
+    if m_map is not None:
+        M = gaussian_pyramid(np.asarray(m_map, dtype=np.float64), levels)
+    else:
+        if m is None:
+            raise ValueError("without m_map the scalar m is needed")
+        M = [np.full(g.shape, float(m)) for g in G]
+    if sigma_map is not None:
+        SG = gaussian_pyramid(sigma_map, levels)
+    else:
+        SG = [np.full(g.shape, float(sigma_r)) for g in G]
     Ct = [gaussian_pyramid(np.cos(omega[k] * I), levels) for k in range(K)]
     St = [gaussian_pyramid(np.sin(omega[k] * I), levels) for k in range(K)]
     LO: List[np.ndarray] = []
@@ -257,17 +319,18 @@ def fourier_llf_adaptive(I: np.ndarray, levels: int, sigma_r: float, m_map: np.n
         shape = G[l].shape
         g = G[l]
         mp = M[l]
+        at_p = alpha_tilde_of(SG[l], K, T)  # alpha~_{k,p} at every level-l pixel
         up_sum = np.zeros(shape)
         for k in range(K):
-            up_sum += alpha_t[k] * (np.sin(omega[k] * g) * expand(Ct[k][l + 1], shape)
-                                    - np.cos(omega[k] * g) * expand(St[k][l + 1], shape))
+            up_sum += at_p[k] * (np.sin(omega[k] * g) * expand(Ct[k][l + 1], shape)
+                                 - np.cos(omega[k] * g) * expand(St[k][l + 1], shape))
         if l == 0:
             Lo = I - expand(G[1], shape) + mp * up_sum
         else:
             here_sum = np.zeros(shape)
             for k in range(K):
-                here_sum += alpha_t[k] * (np.sin(omega[k] * g) * Ct[k][l]
-                                          - np.cos(omega[k] * g) * St[k][l])
+                here_sum += at_p[k] * (np.sin(omega[k] * g) * Ct[k][l]
+                                       - np.cos(omega[k] * g) * St[k][l])
             Lo = G[l] - mp * here_sum - expand(G[l + 1], shape) + mp * up_sum
         LO.append(Lo)
     LO.append(G[levels - 1])
@@ -301,19 +364,22 @@ def naive_llf(I: np.ndarray, levels: int,
     return collapse(LO)
 
 
-def naive_llf_adaptive(I: np.ndarray, levels: int,
-                       remap: Callable[[np.ndarray, float, float], np.ndarray],
-                       m_map: np.ndarray) -> np.ndarray:
-    """Naive LLF whose remap at level-l pixel p uses m = G_l[m_map]_p."""
+def naive_llf_adaptive(I: np.ndarray, levels: int, remap: Callable[..., np.ndarray],
+                       m_map) -> np.ndarray:
+    """Naive LLF whose remap at level-l pixel p takes the per-pixel parameters
+    G_l[map]_p: remap(I, g, v) for one map, remap(I, g, v1, v2, ...) when m_map is
+    a tuple of maps."""
     I = np.asarray(I, dtype=np.float64)
     G = gaussian_pyramid(I, levels)
-    M = gaussian_pyramid(np.asarray(m_map, dtype=np.float64), levels)
+    maps = m_map if isinstance(m_map, (tuple, list)) else (m_map,)
+    P = [gaussian_pyramid(np.asarray(mm, dtype=np.float64), levels) for mm in maps]
     LO: List[np.ndarray] = []
     for l in range(levels - 1):
         out = np.empty_like(G[l])
         for y in range(G[l].shape[0]):
             for x in range(G[l].shape[1]):
-                Gr = gaussian_pyramid(remap(I, G[l][y, x], M[l][y, x]), l + 2)
+                vals = [Pm[l][y, x] for Pm in P]
+                Gr = gaussian_pyramid(remap(I, G[l][y, x], *vals), l + 2)
                 lap = Gr[l] - expand(Gr[l + 1], Gr[l].shape)
                 out[y, x] = lap[y, x]
         LO.append(out)
@@ -347,6 +413,28 @@ def fast_llf(I: np.ndarray, levels: int, remap: Callable[[np.ndarray, float], np
         LO.append((1.0 - a) * lo + a * hi)
     LO.append(G[levels - 1])
     return collapse(LO)
+
+
+def variance_boost_map(I: np.ndarray, radius: int, m_max: float, v_half: float) -> np.ndarray:
+    """Boost map for pixel-by-pixel enhancement driven by local variance (Sec. IV,
+    Fig. 5: the enhancement follows the variance of the pixels in a local
+    window, small where the variance is low).  Reading: the window is the
+    (2 radius + 1)^2 square around p with reflect-101 borders, v_p its population
+    variance, and m_p = m_max v_p / (v_p + v_half): 0 on flat areas, m_max / 2 at
+    v_p = v_half, approaching m_max on strong texture.  Plain loops: the mean of
+    the window first, then the mean squared deviation from it."""
+    I = np.asarray(I, dtype=np.float64)
+    H, W = I.shape
+    out = np.empty_like(I)
+    for y in range(H):
+        rows = [fold_index(y + d, H) for d in range(-radius, radius + 1)]
+        for x in range(W):
+            cols = [fold_index(x + d, W) for d in range(-radius, radius + 1)]
+            win = I[np.ix_(rows, cols)]
+            mean = win.sum() / win.size
+            v = ((win - mean) ** 2).sum() / win.size
+            out[y, x] = m_max * v / (v + v_half)
+    return out
 
 
 # --------------------------------------------------------------------------- #
