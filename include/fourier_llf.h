@@ -59,10 +59,13 @@ typedef enum {
 
 typedef struct fllf_ctx fllf_ctx; /* opaque, host-side state only */
 
-/* One image to filter (Sec. II-A problem statement: image, levels, sigma_r, m, K). */
+/* One image to filter (Sec. II-A problem statement: image, levels, sigma_r, m, K).
+ * Zero-initialise the struct: every field added after m_map means "dense" or
+ * "absent" when 0. */
 typedef struct {
-  const float *in;   /* device; planar channels x height x width float32, dense rows */
-  float *out;        /* device; same layout as in; must not overlap in or the workspace */
+  const float *in;   /* device; planar channels x height x width float32 (pitches below) */
+  float *out;        /* device; channels x height x width float32 (pitches below); must not
+                        overlap in, another job's images or the workspace */
   int32_t width;     /* >= 1 */
   int32_t height;    /* >= 1 */
   int32_t channels;  /* >= 1; each channel is filtered independently */
@@ -77,7 +80,28 @@ typedef struct {
   const float *m_map;/* optional device map height x width of per-pixel boosts m_p
                         (pixel-by-pixel form, Sec. III-B); NULL -> the scalar m.
                         Shared by all channels.  At level l the boost of a level-l
-                        pixel is the Gaussian pyramid value G_l[m_map] there. */
+                        pixel is the Gaussian pyramid value G_l[m_map] there.
+                        Dense rows (row pitch = width). */
+  /* Strided images (Sec. II-A takes an image as it is stored): element pitches,
+   * 0 = dense.  A crop or other view of a larger tensor is filtered in place
+   * of a copy. */
+  int64_t row_pitch;       /* elements between rows of in; 0 -> width; else >= width */
+  int64_t plane_pitch;     /* elements between channels of in; 0 -> row_pitch * height */
+  int64_t out_row_pitch;   /* elements between rows of out; 0 -> width; else >= width */
+  int64_t out_plane_pitch; /* elements between channels of out; 0 -> out_row_pitch * height;
+                              the channels of out must not overlap: either stacked
+                              (>= (height-1)*out_row_pitch + width) or row-interleaved
+                              (>= width, with out_row_pitch >= (channels-1)*out_plane_pitch + width) */
+  const float *sigma_map;  /* optional device map height x width (dense rows) of per-pixel
+                              range scales sigma_p (pixel-by-pixel alpha~_{k,p}, Sec. III-B);
+                              NULL -> the scalar sigma_r.  Shared by all channels; at level l
+                              the range scale of a level-l pixel is G_l[sigma_map] there.
+                              With a map, sigma_r is the smallest value the map holds and
+                              sigma_max the largest (both > 0): one period T serves every
+                              pixel, fitted by Eq. (12) with each of its two terms taken at
+                              the scale where it is largest (period_T overrides). */
+  double sigma_max;        /* with sigma_map: the largest range scale in the map (>= sigma_r);
+                              ignored without a map */
 } fllf_job;
 
 /* Create a context bound to HIP device `device` that stores the Fourier

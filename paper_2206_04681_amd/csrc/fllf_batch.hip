@@ -86,10 +86,8 @@ void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning 
     if (it.P->levels == 1) {
       BatchLaunch b{};
       b.kind = 2;
-      b.copy_src = it.P->in;
-      b.copy_dst = it.P->out;
-      b.copy_bytes = it.P->lv[0].n * it.P->C * sizeof(float);
-      b.bytes = 2.0 * b.copy_bytes;
+      b.copy = it.P->copy;
+      b.bytes = 2.0 * (double)(it.P->lv[0].n * it.P->C * sizeof(float));
       out->launches.push_back(b);
       continue;
     }

@@ -70,7 +70,8 @@ struct fllf_ctx {
   int device;
   fllf_storage storage;
   std::string last_error;
-  EventTimer *timer = nullptr;
+  EventTimer *timer = nullptr;  // records kept until read
+  bool timing_on = false;       // launches are bracketed only while enabled
   fllf::Tuning tune;
   // pinned host staging of the batch table; stage_ev marks the end of its last copy
   void *stage = nullptr;
@@ -187,7 +188,7 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
     Level &L = p->lv[l];
     L.w = w;
     L.h = h;
-    L.pitch = l == 0 ? w : (int)align_up((size_t)w, 64);
+    L.pitch = l == 0 ? (int)job_in_rp(job) : (int)align_up((size_t)w, 64);
     L.n = (size_t)w * h;
     const size_t g_plane = align_up((size_t)L.pitch * h * 4);
     const size_t cs_plane = align_up((size_t)L.pitch * h * pair_bytes * job.K);
@@ -212,6 +213,19 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
     h = (h + 1) / 2;
   }
   p->bytes = off - base;
+  p->in_cs = (size_t)job_in_pp(job);
+  p->out_cs = (size_t)job_out_pp(job);
+  p->out_pitch = (int)job_out_rp(job);
+  CopyDesc &cp = p->copy;
+  cp.src = job.in;
+  cp.dst = job.out;
+  cp.w_bytes = (size_t)job.width * sizeof(float);
+  cp.h = (size_t)job.height;
+  cp.spitch = (size_t)job_in_rp(job) * sizeof(float);
+  cp.dpitch = (size_t)job_out_rp(job) * sizeof(float);
+  cp.sstride = p->in_cs * sizeof(float);
+  cp.dstride = p->out_cs * sizeof(float);
+  cp.C = job.channels;
 
   const double T = job.period_T > 0.0 ? job.period_T : fit_period(job.sigma_r, job.K, job.range_R);
   double at[kMaxK];
@@ -237,10 +251,26 @@ const char *const kHalfNames[kMaxLevels] = {
     "half_l0", "half_l1", "half_l2",  "half_l3",  "half_l4",  "half_l5",  "half_l6",  "half_l7",
     "half_l8", "half_l9", "half_l10", "half_l11", "half_l12", "half_l13", "half_l14", "half_l15"};
 
+// Dense images go as one copy, evenly spaced planes as one 2-D copy of
+// C x h rows, anything else as one 2-D copy per channel.
+hipError_t copy_image(const CopyDesc &d, hipStream_t st) {
+  const bool dense = d.spitch == d.w_bytes && d.dpitch == d.w_bytes && d.sstride == d.w_bytes * d.h &&
+                     d.dstride == d.w_bytes * d.h;
+  if (dense)
+    return hipMemcpyAsync(d.dst, d.src, d.w_bytes * d.h * d.C, hipMemcpyDeviceToDevice, st);
+  if (d.sstride == d.spitch * d.h && d.dstride == d.dpitch * d.h)
+    return hipMemcpy2DAsync(d.dst, d.dpitch, d.src, d.spitch, d.w_bytes, d.h * d.C, hipMemcpyDeviceToDevice, st);
+  for (int c = 0; c < d.C; ++c) {
+    const hipError_t e = hipMemcpy2DAsync((char *)d.dst + c * d.dstride, d.dpitch, (const char *)d.src + c * d.sstride,
+                                          d.spitch, d.w_bytes, d.h, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_reparam(const JobPlan &P, fllf_storage storage, char *ws, hipStream_t st, LaunchHook *h,
                           const Tuning &tu) {
-  if (P.levels == 1)
-    return hipMemcpyAsync(P.out, P.in, P.lv[0].n * P.C * sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (P.levels == 1) return copy_image(P.copy, st);
   switch (storage) {
     case FLLF_STORE_F16: return launch_reparam_f16(P, ws, st, h, tu);
     case FLLF_STORE_BF16: return launch_reparam_bf16(P, ws, st, h, tu);
@@ -250,8 +280,7 @@ hipError_t launch_reparam(const JobPlan &P, fllf_storage storage, char *ws, hipS
 
 hipError_t launch_job(const JobPlan &P, fllf_storage storage, char *ws, hipStream_t st, LaunchHook *h,
                       const Tuning &tu) {
-  if (P.levels == 1)
-    return hipMemcpyAsync(P.out, P.in, P.lv[0].n * P.C * sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (P.levels == 1) return copy_image(P.copy, st);
   switch (storage) {
     case FLLF_STORE_F16: return launch_job_f16(P, ws, st, h, tu);
     case FLLF_STORE_BF16: return launch_job_bf16(P, ws, st, h, tu);
@@ -313,21 +342,49 @@ static fllf_status validate(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_sto
         return fail(ctx, FLLF_EINVAL, "job %d: %d x %d with K=%d needs a level-1 plane of %llu bytes (limit 4 GiB)",
                     i, j.width, j.height, j.K, (unsigned long long)rec_plane);
     }
-    const size_t bytes = (size_t)j.width * j.height * j.channels * sizeof(float);
-    const char *a = (const char *)j.in, *b = (const char *)j.out;
-    if (a < b + bytes && b < a + bytes)
+    // pitches: rows at least as long as the image; the output's channels must
+    // not share an element (stacked planes or row-interleaved channels); every
+    // plane is addressed with 32-bit byte offsets from its first element
+    if (j.row_pitch < 0 || (j.row_pitch > 0 && j.row_pitch < j.width) || j.plane_pitch < 0 ||
+        j.out_row_pitch < 0 || (j.out_row_pitch > 0 && j.out_row_pitch < j.width) || j.out_plane_pitch < 0)
+      return fail(ctx, FLLF_EINVAL, "job %d: pitches must be 0 (dense) or rows of at least width=%d elements", i,
+                  j.width);
+    const int64_t irp = fllf::job_in_rp(j), orp = fllf::job_out_rp(j), opp = fllf::job_out_pp(j);
+    const int64_t kPlaneLimit = (int64_t)1 << 30;  // elements: 4 GiB of float32
+    if (irp > kPlaneLimit || orp > kPlaneLimit || (int64_t)(j.height - 1) * irp + j.width > kPlaneLimit ||
+        (int64_t)(j.height - 1) * orp + j.width > kPlaneLimit || fllf::job_in_pp(j) > ((int64_t)1 << 46) ||
+        opp > ((int64_t)1 << 46))
+      return fail(ctx, FLLF_EINVAL, "job %d: a channel plane spans more than 2^30 elements", i);
+    if (j.channels > 1) {
+      const bool stacked = opp >= (int64_t)(j.height - 1) * orp + j.width;
+      const bool interleaved = opp >= j.width && orp >= (int64_t)(j.channels - 1) * opp + j.width;
+      if (!stacked && !interleaved)
+        return fail(ctx, FLLF_EINVAL, "job %d: out_plane_pitch %lld makes the output's channels overlap", i,
+                    (long long)opp);
+    }
+    if (fllf::spans_overlap(j.in, fllf::in_span(j), j.out, fllf::out_span(j)))
       return fail(ctx, FLLF_EINVAL, "job %d: in and out overlap", i);
+    if (fllf::spans_overlap(j.m_map, fllf::map_span(j), j.out, fllf::out_span(j)))
+      return fail(ctx, FLLF_EINVAL, "job %d: m_map and out overlap", i);
+    if (fllf::spans_overlap(j.sigma_map, fllf::map_span(j), j.out, fllf::out_span(j)))
+      return fail(ctx, FLLF_EINVAL, "job %d: sigma_map and out overlap", i);
+    if (j.sigma_map) {
+      if (!is_finite(j.sigma_max) || j.sigma_max < j.sigma_r)
+        return fail(ctx, FLLF_EINVAL, "job %d: with sigma_map, sigma_max must be finite and >= sigma_r", i);
+      return fail(ctx, FLLF_EUNSUPPORTED, "job %d: sigma_map is not supported", i);
+    }
   }
-  // in a batch every output must be disjoint from every other job's input and output
+  // in a batch every output must be disjoint from every other job's images
   for (int i = 0; i < n && n > 1; ++i) {
-    const char *oi = (const char *)jobs[i].out;
-    const size_t bi = (size_t)jobs[i].width * jobs[i].height * jobs[i].channels * sizeof(float);
+    const size_t bi = fllf::out_span(jobs[i]);
     for (int j = 0; j < n; ++j) {
       if (j == i) continue;
-      const size_t bj = (size_t)jobs[j].width * jobs[j].height * jobs[j].channels * sizeof(float);
-      const char *ij = (const char *)jobs[j].in, *oj = (const char *)jobs[j].out;
-      if ((oi < ij + bj && ij < oi + bi) || (oi < oj + bj && oj < oi + bi))
-        return fail(ctx, FLLF_EINVAL, "job %d: output overlaps job %d's input or output", i, j);
+      const fllf_job &b = jobs[j];
+      if (fllf::spans_overlap(jobs[i].out, bi, b.in, fllf::in_span(b)) ||
+          fllf::spans_overlap(jobs[i].out, bi, b.out, fllf::out_span(b)) ||
+          fllf::spans_overlap(jobs[i].out, bi, b.m_map, fllf::map_span(b)) ||
+          fllf::spans_overlap(jobs[i].out, bi, b.sigma_map, fllf::map_span(b)))
+        return fail(ctx, FLLF_EINVAL, "job %d: output overlaps job %d's images", i, j);
     }
   }
   return FLLF_OK;
@@ -340,7 +397,7 @@ namespace fllf {
 fllf_storage ctx_storage(const fllf_ctx *ctx) { return ctx->storage; }
 int ctx_device(const fllf_ctx *ctx) { return ctx->device; }
 const Tuning &ctx_tuning(const fllf_ctx *ctx) { return ctx->tune; }
-LaunchHook *ctx_hook(fllf_ctx *ctx) { return ctx->timer; }
+LaunchHook *ctx_hook(fllf_ctx *ctx) { return ctx->timing_on ? ctx->timer : nullptr; }
 
 fllf_status ctx_fail(fllf_ctx *ctx, fllf_status st, const char *fmt, ...) {
   char buf[512];
@@ -408,10 +465,8 @@ void fourier_llf_destroy(fllf_ctx *ctx) {
 fllf_status fourier_llf_timing_enable(fllf_ctx *ctx, int enable) {
   if (!ctx) return fail(nullptr, FLLF_EINVAL, "timing_enable: ctx is NULL");
   if (enable && !ctx->timer) ctx->timer = new EventTimer();
-  if (!enable && ctx->timer && ctx->timer->recs.empty()) {
-    delete ctx->timer;
-    ctx->timer = nullptr;
-  }
+  ctx->timing_on = enable != 0;
+  // disabled: no further launch is hooked; unread records stay for timing_read
   if (!enable && ctx->timer) ctx->timer->pending = nullptr;
   return FLLF_OK;
 }
@@ -515,14 +570,14 @@ static fllf_status prepare(fllf_ctx *ctx, const char *who, const fllf_job *jobs,
     return need > 0 && q && q < wsb + need && wsb < q + bytes;
   };
   for (int i = 0; i < n; ++i) {
-    const size_t plane = (size_t)jobs[i].width * jobs[i].height * sizeof(float);
-    const size_t ob = plane * jobs[i].channels;
-    if (hits(jobs[i].out, ob))
+    if (hits(jobs[i].out, fllf::out_span(jobs[i])))
       return fail(ctx, FLLF_EINVAL, "%s: job %d output overlaps the workspace", who, i);
-    if (hits(jobs[i].in, ob))
+    if (hits(jobs[i].in, fllf::in_span(jobs[i])))
       return fail(ctx, FLLF_EINVAL, "%s: job %d input overlaps the workspace", who, i);
-    if (hits(jobs[i].m_map, plane))
+    if (hits(jobs[i].m_map, fllf::map_span(jobs[i])))
       return fail(ctx, FLLF_EINVAL, "%s: job %d boost map overlaps the workspace", who, i);
+    if (hits(jobs[i].sigma_map, fllf::map_span(jobs[i])))
+      return fail(ctx, FLLF_EINVAL, "%s: job %d range-scale map overlaps the workspace", who, i);
   }
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "%s: hipSetDevice: %s", who, hipGetErrorString(e));
@@ -578,7 +633,7 @@ fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *wo
   std::vector<fllf::JobPlan> plans;
   fllf_status st = prepare(ctx, "run", jobs, n, workspace, ws_bytes, &plans);
   if (st != FLLF_OK) return st;
-  return enqueue(ctx, plans, workspace, (hipStream_t)hip_stream, ctx->tune, ctx->timer);
+  return enqueue(ctx, plans, workspace, (hipStream_t)hip_stream, ctx->tune, fllf::ctx_hook(ctx));
 }
 
 fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_job *next, void *workspace,
@@ -614,7 +669,7 @@ fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_
     }
     P.coefs.at[k] = (float)at_next[k];
   }
-  hipError_t e = fllf::launch_reparam(P, ctx->storage, (char *)workspace, (hipStream_t)hip_stream, ctx->timer,
+  hipError_t e = fllf::launch_reparam(P, ctx->storage, (char *)workspace, (hipStream_t)hip_stream, fllf::ctx_hook(ctx),
                                       ctx->tune);
   if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "reparam: launch failed: %s", hipGetErrorString(e));
   return FLLF_OK;

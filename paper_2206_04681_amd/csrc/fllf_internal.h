@@ -33,7 +33,7 @@ struct Coefs {
 // Geometry and workspace placement of one pyramid level of one job.
 struct Level {
   int w, h;
-  int pitch;         // elements per row: level 0 = the caller's dense rows (w),
+  int pitch;         // elements per row: level 0 = the input's row pitch,
                      // levels >= 1 = w rounded up to 64 (aligned, even: vector loads)
   size_t n;          // w * h
   // byte offsets into the workspace (levels >= 1), per-channel strides in elements
@@ -46,6 +46,16 @@ struct Level {
   size_t cs_cstride; // pair elements between channels
 };
 
+// A strided image copy (a job with a single level: the output is the input):
+// C planes of h rows of w_bytes each; pitches and strides in bytes.
+struct CopyDesc {
+  const void *src;
+  void *dst;
+  size_t w_bytes, h, spitch, dpitch, sstride, dstride;
+  int C;
+};
+hipError_t copy_image(const CopyDesc &d, hipStream_t stream);
+
 struct JobPlan {
   int levels, K, C;
   int dwp;           // dwords per stored (C~, S~) pair: 2 (float32) or 1 (16-bit)
@@ -55,7 +65,33 @@ struct JobPlan {
   const float *in;
   float *out;
   const float *m_map;
+  // level-0 images: element pitches of the caller's rows and channels (the
+  // input's row pitch is also lv[0].pitch); the maps have dense rows
+  size_t in_cs, out_cs;
+  int out_pitch;
+  CopyDesc copy;     // the whole job when levels == 1
 };
+
+// Element pitches of a job's images with the dense defaults applied.
+inline int64_t job_in_rp(const fllf_job &j) { return j.row_pitch > 0 ? j.row_pitch : j.width; }
+inline int64_t job_in_pp(const fllf_job &j) { return j.plane_pitch > 0 ? j.plane_pitch : job_in_rp(j) * j.height; }
+inline int64_t job_out_rp(const fllf_job &j) { return j.out_row_pitch > 0 ? j.out_row_pitch : j.width; }
+inline int64_t job_out_pp(const fllf_job &j) {
+  return j.out_plane_pitch > 0 ? j.out_plane_pitch : job_out_rp(j) * j.height;
+}
+// Bytes from an image's first element to one past its last (the span overlap
+// checks use): channels x rows x width at the given element pitches.
+inline size_t image_span(const fllf_job &j, int64_t rp, int64_t pp) {
+  return (size_t)((int64_t)(j.channels - 1) * pp + (int64_t)(j.height - 1) * rp + j.width) * sizeof(float);
+}
+inline size_t in_span(const fllf_job &j) { return image_span(j, job_in_rp(j), job_in_pp(j)); }
+inline size_t out_span(const fllf_job &j) { return image_span(j, job_out_rp(j), job_out_pp(j)); }
+inline size_t map_span(const fllf_job &j) { return (size_t)j.width * j.height * sizeof(float); }
+// True when [p, p + a) and [q, q + b) share a byte (null pointers share none).
+inline bool spans_overlap(const void *p, size_t a, const void *q, size_t b) {
+  const char *x = (const char *)p, *y = (const char *)q;
+  return x && y && x < y + b && y < x + a;
+}
 
 // Host fit in float64 (Eq. (9)-(12)).
 double fit_period(double sigma_r, int K, double R);
@@ -124,9 +160,7 @@ struct BatchLaunch {
   size_t args_off;    // byte offsets of the argument array and of the njobs + 1 wave offsets
   size_t start_off;
   double bytes;       // algorithmic bytes of the launch
-  const void *copy_src;  // kind 2
-  void *copy_dst;
-  size_t copy_bytes;
+  CopyDesc copy;      // kind 2
 };
 
 struct BatchSchedule {

@@ -348,6 +348,8 @@ constexpr int min_waves_per_simd(int KM) { return KM <= 8 ? 2 : 1; }
 struct Geom {
   int Wf, Hf, Wc, Hc;  // fine and coarse sizes
   int pf, pc;          // row pitches (pixels) of the fine and coarse planes
+  int po, pm;          // row pitches of the fine output (up passes) and of the fine
+                       // boost plane: pf, except at level 0 (the caller's images)
   int nstrips, nsegs;  // column strips (62 coarse columns each) and row segments
   int S;               // coarse rows per segment
   int C;               // channels
@@ -536,7 +538,7 @@ struct DownWave {
   __device__ inline void load(RowIn &d, int r) const {
     const uint32_t fr = (uint32_t)reflect(r, a.g.Hf);
     ld_f2<BORDER>(Plane(gf), fr * (uint32_t)a.g.pf * 4u, d.g0, d.g1);
-    if (MAP) ld_f2<BORDER>(Plane(a.mf), fr * (uint32_t)a.g.pf * 4u, d.m0, d.m1);
+    if (MAP) ld_f2<BORDER>(Plane(a.mf), fr * (uint32_t)a.g.pm * 4u, d.m0, d.m1);
     if (!L0) {
       const Plane p(csf);
       const uint32_t so = fr * (uint32_t)a.g.pf * rec;
@@ -981,7 +983,7 @@ struct UpWave {
     gfp = a.gf + (size_t)c * a.gf_cs;
     outp = a.out + (size_t)c * a.out_cs;
     // the caller's output (level 0) has arbitrary pitch and alignment
-    vec_f = !L0 || (((g.pf & 1) == 0) && ((reinterpret_cast<uintptr_t>(outp) & 7) == 0));
+    vec_f = !L0 || (((g.po & 1) == 0) && ((reinterpret_cast<uintptr_t>(outp) & 7) == 0));
     gc = a.gc + (size_t)c * a.gc_cs;
     oc = HASD ? a.oc + (size_t)c * a.oc_cs : nullptr;
     csc = a.csc + (size_t)c * a.csc_cs;
@@ -1067,7 +1069,7 @@ struct UpWave {
       const uint32_t so = rr[q] * (uint32_t)a.g.pf * 4u;
       ld_f2<BORDER>(Plane(gfp), so, d.g[2 * q], d.g[2 * q + 1]);
       if (!L0) ld_f2<BORDER>(Plane(base), so, d.b[2 * q], d.b[2 * q + 1]);
-      if (MAP) ld_f2<BORDER>(Plane(a.mf), so, d.m[2 * q], d.m[2 * q + 1]);
+      if (MAP) ld_f2<BORDER>(Plane(a.mf), rr[q] * (uint32_t)a.g.pm * 4u, d.m[2 * q], d.m[2 * q + 1]);
     }
   }
 
@@ -1152,7 +1154,7 @@ struct UpWave {
       if (writer) {
         const uint32_t r0 = 2 * i;
         const bool row1 = (int)r0 + 1 < g.Hf;
-        const uint32_t s0 = r0 * (uint32_t)g.pf * 4u, s1 = s0 + (uint32_t)g.pf * 4u;
+        const uint32_t s0 = r0 * (uint32_t)g.po * 4u, s1 = s0 + (uint32_t)g.po * 4u;
         if (two && vec_f) {
           op.st2(make_float2(o[0], o[1]), vx, s0);
           if (row1) op.st2(make_float2(o[2], o[3]), vx, s1);
@@ -1259,6 +1261,8 @@ inline Geom make_geom(const Level &f, const Level &cl, int C, int S, int sw) {
   g.Hc = cl.h;
   g.pf = f.pitch;
   g.pc = cl.pitch;
+  g.po = f.pitch;
+  g.pm = f.pitch;
   g.nstrips = (cl.w + sw - 1) / sw;
   g.S = S;
   g.nsegs = (cl.h + S - 1) / S;
@@ -1345,7 +1349,7 @@ inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const
   };
   DownArgs a{};
   a.gf = l == 0 ? P.in : (const float *)(ws + lv[l].off_g);
-  a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  a.gf_cs = l == 0 ? P.in_cs : lv[l].g_cstride;
   a.csf = l == 0 ? nullptr : (const uint32_t *)(ws + lv[l].off_cs);
   a.csf_cs = lv[l].cs_cstride * dwp;
   a.mf = M(l);
@@ -1358,6 +1362,7 @@ inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const
   a.af_cs = lv[l].g_cstride;
   a.minus_g = l == 1 && fused_level(P, 1) && L > 2 ? 1 : 0;
   a.g = pass_geom(P, l, true, tu);
+  if (l == 0) a.g.pm = lv[0].w;  // the caller's map has dense rows
   a.cf = P.coefs;
   return a;
 }
@@ -1368,9 +1373,9 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
   const bool map = P.m_map != nullptr;
   UpArgs a{};
   a.base = l == 0 ? P.in : (const float *)(ws + lv[l].off_o);
-  a.base_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  a.base_cs = l == 0 ? P.in_cs : lv[l].g_cstride;
   a.gf = l == 0 ? P.in : (const float *)(ws + lv[l].off_g);
-  a.gf_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  a.gf_cs = l == 0 ? P.in_cs : lv[l].g_cstride;
   a.mf = !map ? nullptr : l == 0 ? P.m_map : (const float *)(ws + lv[l].off_m);
   a.gc = (const float *)(ws + lv[l + 1].off_g);
   a.gc_cs = lv[l + 1].g_cstride;
@@ -1380,7 +1385,7 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
   a.csc = (const uint32_t *)(ws + lv[l + 1].off_cs);
   a.csc_cs = lv[l + 1].cs_cstride * dwp;
   a.out = l == 0 ? P.out : (float *)(ws + lv[l].off_o);
-  a.out_cs = l == 0 ? lv[0].n : lv[l].g_cstride;
+  a.out_cs = l == 0 ? P.out_cs : lv[l].g_cstride;
   // the normal sequence leaves L_1[O] - G_1 in the O_1 slot when level 1 is
   // fused; up(0) adds EXPAND(O_2) itself
   a.oc_minus_g = l == 0 && hasd && !reparam && fused_level(P, 1) ? 1 : 0;
@@ -1392,6 +1397,10 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
     a.p2 = lv[2].pitch;
   }
   a.g = pass_geom(P, l, false, tu, reparam);
+  if (l == 0) {  // the caller's output and map rows
+    a.g.po = P.out_pitch;
+    a.g.pm = lv[0].w;
+  }
   a.cf = P.coefs;
   return a;
 }
@@ -1621,7 +1630,7 @@ hipError_t launch_batch_storage(const BatchSchedule &s, char *ws, hipStream_t st
     if (hook) hook->before(st);
     hipError_t e = hipSuccess;
     if (b.kind == 2) {
-      e = hipMemcpyAsync(b.copy_dst, b.copy_src, b.copy_bytes, hipMemcpyDeviceToDevice, st);
+      e = copy_image(b.copy, st);
     } else if (b.kind == 1 && b.fuse && !b.l0) {  // the collapse does not depend on K
       const UpArgs *args = (const UpArgs *)(ws + b.args_off);
       const uint32_t *start = (const uint32_t *)(ws + b.start_off);

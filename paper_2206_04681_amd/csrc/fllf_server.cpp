@@ -201,12 +201,9 @@ fllf_status fourier_llf_server_submit(fllf_server *s, const fllf_job *job, uint6
   const fllf_storage storage = fllf::ctx_storage(ctx);
   fllf_status st = fllf::validate_jobs(ctx, job, 1, storage);
   if (st != FLLF_OK) return st;
-  const size_t plane = (size_t)job->width * job->height * sizeof(float);
-  auto hits = [&](const void *p, size_t bytes) {
-    const char *q = (const char *)p;
-    return q && q < s->base + s->bytes && s->base < q + bytes;
-  };
-  if (hits(job->out, plane * job->channels) || hits(job->in, plane * job->channels) || hits(job->m_map, plane))
+  auto hits = [&](const void *p, size_t bytes) { return fllf::spans_overlap(p, bytes, s->base, s->bytes); };
+  if (hits(job->out, fllf::out_span(*job)) || hits(job->in, fllf::in_span(*job)) ||
+      hits(job->m_map, fllf::map_span(*job)) || hits(job->sigma_map, fllf::map_span(*job)))
     return fllf::ctx_fail(ctx, FLLF_EINVAL, "server_submit: the job's images overlap the arena");
   Job *j = new Job();
   j->job = *job;

@@ -68,6 +68,12 @@ class FllfJob(ctypes.Structure):
         ("range_R", ctypes.c_double),
         ("period_T", ctypes.c_double),
         ("m_map", ctypes.c_void_p),
+        ("row_pitch", ctypes.c_int64),
+        ("plane_pitch", ctypes.c_int64),
+        ("out_row_pitch", ctypes.c_int64),
+        ("out_plane_pitch", ctypes.c_int64),
+        ("sigma_map", ctypes.c_void_p),
+        ("sigma_max", ctypes.c_double),
     ]
 
 
@@ -207,11 +213,16 @@ class Job:
     T: float = 0.0
     out: Optional["object"] = None
     m_map: Optional["object"] = None
+    sigma_map: Optional["object"] = None
+    sigma_max: float = 0.0
 
 
 def make_job(in_ptr: int, out_ptr: int, width: int, height: int, channels: int, levels: int,
              sigma_r: float, m: float, K: int, R: float = 1.0, T: float = 0.0,
-             m_map_ptr: int = 0) -> FllfJob:
+             m_map_ptr: int = 0, pitches: Sequence[int] = (0, 0, 0, 0), sigma_map_ptr: int = 0,
+             sigma_max: float = 0.0) -> FllfJob:
+    """pitches = (row_pitch, plane_pitch, out_row_pitch, out_plane_pitch) in
+    elements, 0 = dense."""
     j = FllfJob()
     j.in_ = in_ptr
     j.out = out_ptr
@@ -219,7 +230,22 @@ def make_job(in_ptr: int, out_ptr: int, width: int, height: int, channels: int, 
     j.levels, j.K, j.flags = int(levels), int(K), 0
     j.sigma_r, j.m, j.range_R, j.period_T = float(sigma_r), float(m), float(R), float(T)
     j.m_map = m_map_ptr or None
+    j.row_pitch, j.plane_pitch, j.out_row_pitch, j.out_plane_pitch = (int(p) for p in pitches)
+    j.sigma_map = sigma_map_ptr or None
+    j.sigma_max = float(sigma_max)
     return j
+
+
+def _pitches(t) -> Tuple[int, int]:
+    """(row, plane) element pitches of a (C, H, W) or (H, W) float32 view whose
+    rows are contiguous; raises for other layouts."""
+    if t.dim() not in (2, 3):
+        raise ValueError("images must be (H, W) or (C, H, W)")
+    if t.stride(-1) != 1 and t.shape[-1] > 1:
+        raise ValueError("image rows must be contiguous (last stride 1)")
+    row = t.stride(-2) if t.shape[-2] > 1 else t.shape[-1]
+    plane = t.stride(0) if t.dim() == 3 and t.shape[0] > 1 else 0
+    return int(row), int(plane)
 
 
 class FourierLLF:
@@ -253,25 +279,31 @@ class FourierLLF:
         x = job.x
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32):
             raise TypeError("x must be a CUDA float32 tensor")
-        if not x.is_contiguous():
-            raise ValueError("x must be contiguous")
         if x.dim() == 2:
             C, H, W = 1, x.shape[0], x.shape[1]
         elif x.dim() == 3:
             C, H, W = x.shape
         else:
             raise ValueError("x must be (H, W) or (C, H, W)")
-        out = job.out if job.out is not None else torch.empty_like(x)
-        if out.shape != x.shape or out.dtype != torch.float32 or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float32 tensor shaped like x")
+        out = job.out if job.out is not None else torch.empty(x.shape, dtype=torch.float32, device=x.device)
+        if out.shape != x.shape or out.dtype != torch.float32 or not out.is_cuda:
+            raise ValueError("out must be a CUDA float32 tensor shaped like x")
+        irp, ipp = _pitches(x)
+        orp, opp = _pitches(out)
         mptr = 0
         if job.m_map is not None:
             mm = job.m_map
             if tuple(mm.shape) != (H, W) or mm.dtype != torch.float32 or not mm.is_contiguous() or not mm.is_cuda:
                 raise ValueError("m_map must be a contiguous CUDA float32 (H, W) tensor")
             mptr = mm.data_ptr()
+        sptr = 0
+        if job.sigma_map is not None:
+            sm = job.sigma_map
+            if tuple(sm.shape) != (H, W) or sm.dtype != torch.float32 or not sm.is_contiguous() or not sm.is_cuda:
+                raise ValueError("sigma_map must be a contiguous CUDA float32 (H, W) tensor")
+            sptr = sm.data_ptr()
         fj = make_job(x.data_ptr(), out.data_ptr(), W, H, C, job.levels, job.sigma_r, job.m, job.K,
-                      job.R, job.T, mptr)
+                      job.R, job.T, mptr, (irp, ipp, orp, opp), sptr, job.sigma_max)
         return fj, out
 
     def workspace_size(self, jobs: Sequence[FllfJob]) -> int:
@@ -286,16 +318,24 @@ class FourierLLF:
             self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         return self._ws
 
-    def run_jobs(self, fjobs: Sequence[FllfJob], workspace=None, stream=None) -> None:
-        """Enqueue already-marshalled jobs on `stream` (default: torch's current stream)."""
+    def run_jobs(self, fjobs: Sequence[FllfJob], workspace=None, stream=None, keep=()) -> None:
+        """Enqueue already-marshalled jobs on `stream` (default: torch's current
+        stream).  On another stream than the current one, the cached workspace and
+        the tensors in `keep` are marked as used by that stream, so that torch's
+        allocator does not hand their memory out again before its work is done."""
         import torch
         arr = _job_array(fjobs)
         need = self.workspace_size(fjobs)
         ws = workspace if workspace is not None else self.workspace(need)
+        current = torch.cuda.current_stream(self.device)
         if stream is None:
-            stream = torch.cuda.current_stream(self.device)
+            stream = current
         sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         _check(lib().fourier_llf_run(self._ctx, arr, len(fjobs), ws.data_ptr(), ws.numel(), sptr), self._ctx)
+        if isinstance(stream, torch.cuda.Stream) and stream != current:
+            for t in (ws,) + tuple(keep):
+                if t is not None:
+                    t.record_stream(stream)
 
     def timing(self, enable: bool) -> None:
         """Bracket every kernel launch with hipEvents on the run's stream."""
@@ -359,16 +399,19 @@ class FourierLLF:
         return Graph(g, ws)
 
     def run(self, x, levels: int, sigma_r: float, m: float, K: int, R: float = 1.0, T: float = 0.0,
-            out=None, m_map=None, stream=None):
-        """Filter one (C, H, W) or (H, W) float32 CUDA tensor; returns the output tensor."""
-        fj, out = self._prepare(Job(x, levels, sigma_r, m, K, R, T, out, m_map))
-        self.run_jobs([fj], stream=stream)
+            out=None, m_map=None, stream=None, sigma_map=None, sigma_max: float = 0.0):
+        """Filter one (C, H, W) or (H, W) float32 CUDA tensor (rows contiguous; a
+        crop or other strided view is read in place) into `out` (a new dense
+        tensor when None; any view with contiguous rows otherwise); returns it."""
+        fj, out = self._prepare(Job(x, levels, sigma_r, m, K, R, T, out, m_map, sigma_map, sigma_max))
+        self.run_jobs([fj], stream=stream, keep=(out, m_map, sigma_map))
         return out
 
     def run_batch(self, jobs: Sequence[Job], stream=None) -> List["object"]:
         """Filter several images (sizes and parameters may differ) in one call."""
         prepared = [self._prepare(j) for j in jobs]
-        self.run_jobs([p[0] for p in prepared], stream=stream)
+        keep = [p[1] for p in prepared] + [j.m_map for j in jobs] + [j.sigma_map for j in jobs]
+        self.run_jobs([p[0] for p in prepared], stream=stream, keep=keep)
         return [p[1] for p in prepared]
 
 

@@ -150,9 +150,10 @@ def test_product_path_does_not_import_oracle():
 
 
 def test_struct_mirrors_match_the_header(F):
-    # fllf_job: 2 pointers, 6 int32, 4 doubles, 1 pointer; fllf_server_stats: 4 int32,
-    # 4 int64, 2 int32, 3 uint64; fllf_kernel_time: char[32], int32, 2 doubles
-    assert ctypes.sizeof(F.FllfJob) == 2 * 8 + 6 * 4 + 4 * 8 + 8
+    # fllf_job: 2 pointers, 6 int32, 4 doubles, 1 pointer, 4 int64, 1 pointer, 1 double;
+    # fllf_server_stats: 4 int32, 4 int64, 2 int32, 3 uint64; fllf_kernel_time:
+    # char[32], int32, 2 doubles
+    assert ctypes.sizeof(F.FllfJob) == 2 * 8 + 6 * 4 + 4 * 8 + 8 + 4 * 8 + 8 + 8
     assert ctypes.sizeof(F.FllfServerStats) == 4 * 4 + 4 * 8 + 2 * 4 + 3 * 8
     assert ctypes.sizeof(F.FllfKernelTime) == 32 + 4 + 4 + 2 * 8
 
@@ -165,3 +166,51 @@ def test_validate_rejects_record_planes_past_32bit_offsets(F):
     assert "4 GiB" in F.last_error()
     # the same image with 16-bit pairs (2 GiB) is accepted
     assert F.validate([_job(F, **big)], "f16") == F.FLLF_OK
+
+
+# --- strided images: row and plane pitches (0 = dense) ---------------------------
+
+def test_validate_accepts_strided_views(F):
+    # a crop of a 3 x 100 x 90 tensor (rows of 90, planes of 9000) into a dense output
+    assert F.validate([_job(F, channels=3, pitches=(90, 9000, 0, 0))]) == F.FLLF_OK
+    # output rows inside a wider tensor; row-interleaved output channels (an H x C x W tensor viewed as C x H x W)
+    assert F.validate([_job(F, channels=3, pitches=(0, 0, 200, 200 * 48))]) == F.FLLF_OK
+    assert F.validate([_job(F, channels=3, pitches=(0, 0, 3 * 64, 64))]) == F.FLLF_OK
+    # any input plane pitch is fine (the input is only read), even planes that share rows
+    assert F.validate([_job(F, channels=3, pitches=(64, 64, 0, 0))]) == F.FLLF_OK
+
+
+@pytest.mark.parametrize("pitches,why", [
+    ((63, 0, 0, 0), "pitches"),              # input rows shorter than the image
+    ((0, 0, 50, 0), "pitches"),              # output rows shorter than the image
+    ((-64, 0, 0, 0), "pitches"),
+    ((0, -1, 0, 0), "pitches"),
+    ((0, 0, 0, 64 * 47), "overlap"),         # output planes one row too close
+    ((0, 0, 2 * 64, 64), "overlap"),         # interleaved output rows too short for 3 channels
+])
+def test_validate_rejects_bad_pitches(F, pitches, why):
+    assert F.validate([_job(F, channels=3, pitches=pitches)]) == F.FLLF_EINVAL
+    assert why in F.last_error()
+
+
+def test_validate_span_of_strided_images(F):
+    # with a row pitch of 1000, the input (0x1000 + 4 x (47 x 1000 + 64) bytes) reaches
+    # an output placed 100 KB further: overlap; dense it does not
+    out = 0x1000 + 100 * 1024
+    assert F.validate([_job(F, out_ptr=out)]) == F.FLLF_OK
+    assert F.validate([_job(F, out_ptr=out, pitches=(1000, 0, 0, 0))]) == F.FLLF_EINVAL
+    assert "overlap" in F.last_error()
+
+
+def test_validate_rejects_planes_past_32bit_offsets(F):
+    # rows of 2^20 elements: 1100 rows exceed the 2^30-element plane limit
+    big = dict(width=64, height=1100, levels=2, out_ptr=0x100000000000)
+    assert F.validate([_job(F, **big, pitches=(1 << 20, 0, 0, 0))]) == F.FLLF_EINVAL
+    assert "2^30" in F.last_error()
+    assert F.validate([_job(F, **big, pitches=(1 << 19, 0, 0, 0))]) == F.FLLF_OK
+
+
+def test_footprint_does_not_depend_on_pitches(F):
+    a = F.footprint([_job(F, channels=3)])
+    b = F.footprint([_job(F, channels=3, pitches=(100, 10000, 128, 128 * 48))])
+    assert a == b

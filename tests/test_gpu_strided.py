@@ -1,0 +1,122 @@
+"""GPU parity of strided images (the row and plane pitches of fllf_job): crops
+and other views of larger tensors are read and written in place.  A strided run
+performs the same arithmetic as a dense one, so its output equals the dense
+run's bit for bit; the crop is also checked against the FP64 oracle on every
+channel, at a size whose level 1 takes the fused path."""
+import numpy as np
+import pytest
+
+from oracle_pool import oracle_channels, report
+from paper_2206_04681_amd.synth import synth_image
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+_CTX = {}
+
+
+def llf(storage="f32"):
+    from paper_2206_04681_amd.fllf import FourierLLF
+    if storage not in _CTX:
+        _CTX[storage] = FourierLLF(storage)
+    return _CTX[storage]
+
+
+def _dense(torch, x, **kw):
+    out = llf(kw.pop("storage", "f32")).run(x.contiguous(), **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+# (big C, H, W), crop origin (y, x), crop (h, w), levels, K, storage.  The first
+# crop's level 1 (700 x 550 x 3 channels) is above 2^20 samples: fused down(1) and
+# up(0) with the level-1 collapse folded in, on an odd input row pitch.
+CROPS = [((3, 1432, 1111), (17, 5), (1400, 1100), 6, 8, "f32"),
+         ((3, 300, 257), (3, 1), (201, 130), 5, 4, "f32"),
+         ((1, 96, 97), (0, 3), (90, 77), 4, 8, "f16"),
+         ((2, 40, 41), (1, 1), (33, 17), 1, 4, "f32")]
+
+
+@pytest.mark.parametrize("big,at,size,L,K,storage", CROPS)
+def test_crop_equals_dense_copy(torch_dev, big, at, size, L, K, storage):
+    torch = torch_dev
+    C, H, W = big
+    full = torch.from_numpy(synth_image(H, W, C, seed=H + W)).cuda()
+    view = full[:, at[0]:at[0] + size[0], at[1]:at[1] + size[1]]
+    assert not view.is_contiguous()
+    kw = dict(levels=L, sigma_r=0.15, m=2.0, K=K)
+    got = llf(storage).run(view, **kw)
+    torch.cuda.synchronize()
+    want = _dense(torch, view, storage=storage, **kw)
+    assert torch.equal(got, want)
+
+
+def test_crop_against_oracle_every_channel(torch_dev):
+    torch = torch_dev
+    (C, H, W), at, (h, w), L, K, _ = CROPS[0]
+    img = synth_image(H, W, C, seed=H + W)
+    full = torch.from_numpy(img).cuda()
+    view = full[:, at[0]:at[0] + h, at[1]:at[1] + w]
+    got = llf().run(view, L, 0.15, 2.0, K)
+    torch.cuda.synchronize()
+    want = oracle_channels(img[:, at[0]:at[0] + h, at[1]:at[1] + w], L, 0.15, 2.0, K)
+    errs, _ = report(f"{h}x{w} crop of {H}x{W} RGB (row pitch {W})", got.cpu().numpy(), want)
+    assert max(errs) <= TOL_F32
+
+
+@pytest.mark.parametrize("layout", ["wide_rows", "interleaved", "odd_pitch"])
+def test_output_into_a_view(torch_dev, layout):
+    torch = torch_dev
+    C, h, w, L = 3, 150, 203, 5
+    x = torch.from_numpy(synth_image(h, w, C, seed=5)).cuda()
+    kw = dict(levels=L, sigma_r=0.1, m=3.0, K=8)
+    want = _dense(torch, x, **kw)
+    sentinel = -7.25
+    if layout == "wide_rows":      # rows of 256 inside a (3, 160, 256) tensor
+        shape, view = (C, 160, 256), lambda b: b[:, 5:5 + h, 40:40 + w]
+    elif layout == "interleaved":  # an (h, C, w) tensor viewed as (C, h, w)
+        shape, view = (h, C, w), lambda b: b.permute(1, 0, 2)
+    else:                          # odd row pitch; a base that is not 8-byte aligned
+        shape, view = (C, h + 2, w + 2), lambda b: b[:, 1:1 + h, 1:1 + w]
+    buf = torch.full(shape, sentinel, device="cuda")
+    out = view(buf)
+    got = llf().run(x, out=out, **kw)
+    torch.cuda.synchronize()
+    assert got.data_ptr() == out.data_ptr()
+    assert torch.equal(out, want)
+    rest = buf.clone()
+    view(rest).fill_(sentinel)
+    assert bool((rest == sentinel).all())  # nothing outside the view was written
+
+
+def test_strided_input_with_boost_map(torch_dev):
+    torch = torch_dev
+    C, h, w = 3, 120, 97
+    full = torch.from_numpy(synth_image(130, 110, C, seed=9)).cuda()
+    view = full[:, 4:4 + h, 7:7 + w]
+    mm = torch.from_numpy(synth_image(h, w, 1, seed=10)[0] * 3.0).cuda()
+    kw = dict(levels=5, sigma_r=0.2, m=0.0, K=8, m_map=mm)
+    got = llf().run(view, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(got, _dense(torch, view, **kw))
+
+
+def test_strided_batch_equals_single_runs(torch_dev):
+    torch = torch_dev
+    from paper_2206_04681_amd.fllf import Job
+    full = torch.from_numpy(synth_image(300, 400, 3, seed=11)).cuda()
+    views = [full[:, 10:210, 20:321], full[1, 50:250, 3:180], full[:, 0:99, 0:99]]
+    params = [(6, 0.1, 3.0, 8), (5, 0.2, 2.0, 4), (1, 0.2, 2.0, 4)]
+    outs = llf().run_batch([Job(v, *p) for v, p in zip(views, params)])
+    torch.cuda.synchronize()
+    for v, p, o in zip(views, params, outs):
+        assert torch.equal(o, _dense(torch, v, levels=p[0], sigma_r=p[1], m=p[2], K=p[3]))
