@@ -127,6 +127,26 @@ fllf_status fourier_llf_workspace_size(const fllf_ctx *ctx, const fllf_job *jobs
 fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
                             size_t ws_bytes, void *hip_stream);
 
+/* ---- a run that allocates nothing ----------------------------------------- */
+
+/* Bytes of the library's own static workspace (256 MiB per device). */
+#define FLLF_STATIC_WORKSPACE_BYTES ((size_t)256 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): filters one
+ * job exactly as fourier_llf_run(ctx, job, 1, ...) does (same kernels, same
+ * result bit for bit) with the workspace taken from an array of
+ * FLLF_STATIC_WORKSPACE_BYTES that the library holds on each device from the
+ * first call on that device until the process ends.  The call itself performs
+ * no device, pinned or heap allocation (context timing hooks are not applied).
+ * Fails with FLLF_ENOMEM, launching nothing, when the job's workspace
+ * (fourier_llf_workspace_size) exceeds the limit.  Every call on a device
+ * shares that device's array: calls whose work may overlap on one device (two
+ * streams, or two host threads) race and must be serialised by the caller,
+ * e.g. on one stream.  The array needs no clearing: each call writes every
+ * workspace element before it reads it.  Asynchronous on hip_stream. */
+fllf_status fourier_llf_run_static(fllf_ctx *ctx, const fllf_job *job, void *hip_stream);
+
 /* ---- re-parameterisation from resident pyramids --------------------------- */
 
 /* After fourier_llf_run(ctx, prev, 1, workspace, ...) the workspace holds the

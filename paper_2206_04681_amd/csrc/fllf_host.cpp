@@ -550,14 +550,10 @@ fllf_status fourier_llf_workspace_size(const fllf_ctx *ctx, const fllf_job *jobs
   return footprint(const_cast<fllf_ctx *>(ctx), jobs, n, ctx->storage, bytes);
 }
 
-// Checks shared by run, autotune and graph capture; plans the jobs.
-static fllf_status prepare(fllf_ctx *ctx, const char *who, const fllf_job *jobs, int n, void *workspace,
-                           size_t ws_bytes, std::vector<fllf::JobPlan> *plans) {
-  if (!ctx) return fail(nullptr, FLLF_EINVAL, "%s: ctx is NULL", who);
-  fllf_status st = validate(ctx, jobs, n, ctx->storage);
-  if (st != FLLF_OK) return st;
-  size_t table = 0, need = 0;
-  plan_all(jobs, n, ctx->storage, plans, &table, &need);
+// The workspace checks shared by every entry point that launches work (need =
+// the planned workspace bytes), then the device made current.
+static fllf_status check_workspace(fllf_ctx *ctx, const char *who, const fllf_job *jobs, int n, void *workspace,
+                                   size_t ws_bytes, size_t need) {
   if (need > 0 && !workspace) return fail(ctx, FLLF_EINVAL, "%s: workspace is NULL", who);
   if (ws_bytes < need)
     return fail(ctx, FLLF_ENOMEM, "%s: workspace has %zu bytes, %zu needed", who, ws_bytes, need);
@@ -585,6 +581,43 @@ static fllf_status prepare(fllf_ctx *ctx, const char *who, const fllf_job *jobs,
   if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "%s: pending HIP error: %s", who, hipGetErrorString(e));
   return FLLF_OK;
 }
+
+// Checks shared by run, autotune and graph capture; plans the jobs.
+static fllf_status prepare(fllf_ctx *ctx, const char *who, const fllf_job *jobs, int n, void *workspace,
+                           size_t ws_bytes, std::vector<fllf::JobPlan> *plans) {
+  if (!ctx) return fail(nullptr, FLLF_EINVAL, "%s: ctx is NULL", who);
+  fllf_status st = validate(ctx, jobs, n, ctx->storage);
+  if (st != FLLF_OK) return st;
+  size_t table = 0, need = 0;
+  plan_all(jobs, n, ctx->storage, plans, &table, &need);
+  return check_workspace(ctx, who, jobs, n, workspace, ws_bytes, need);
+}
+
+}  // extern "C"
+
+namespace fllf {
+
+// One job planned on the stack and launched with no timing hook: no heap, pinned
+// or device allocation on the success path.
+fllf_status run_single(fllf_ctx *ctx, const char *who, const fllf_job &job, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  fllf_status st = validate(ctx, &job, 1, ctx->storage);
+  if (st != FLLF_OK) return st;
+  JobPlan P;
+  plan_job(job, ctx->storage, 0, &P);
+  if (P.bytes > ws_bytes)
+    return fail(ctx, FLLF_ENOMEM, "%s: the job needs %zu bytes of workspace; the limit is %zu", who, P.bytes,
+                ws_bytes);
+  st = check_workspace(ctx, who, &job, 1, ws, ws_bytes, P.bytes);
+  if (st != FLLF_OK) return st;
+  const hipError_t e = launch_job(P, ctx->storage, (char *)ws, stream, nullptr, ctx->tune);
+  if (e != hipSuccess) return fail(ctx, FLLF_EDEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
+  return FLLF_OK;
+}
+
+}  // namespace fllf
+
+extern "C" {
 
 // Copies a batch table into the workspace on `stream` through the context's
 // pinned staging buffer.

@@ -206,5 +206,10 @@ LaunchHook *ctx_hook(fllf_ctx *ctx);
 fllf_status ctx_fail(fllf_ctx *ctx, fllf_status st, const char *fmt, ...);
 // The parameter checks of fourier_llf_run.
 fllf_status validate_jobs(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_storage storage);
+// Validates, plans and enqueues one job in the workspace ws (ws_bytes long), with
+// no heap, pinned or device allocation and no timing hook; `who` names the
+// entry point in error messages.
+fllf_status run_single(fllf_ctx *ctx, const char *who, const fllf_job &job, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
 
 }  // namespace fllf

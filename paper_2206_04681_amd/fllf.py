@@ -31,7 +31,7 @@ EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run
             "fourier_llf_graph_create", "fourier_llf_graph_launch", "fourier_llf_graph_destroy",
             "fourier_llf_server_create", "fourier_llf_server_submit", "fourier_llf_server_step",
             "fourier_llf_server_poll", "fourier_llf_server_stats", "fourier_llf_server_destroy",
-            "fourier_llf_reparam")
+            "fourier_llf_reparam", "fourier_llf_run_static")
 
 # Launch-shape parameters (FLLF_TUNE_*): target waves of the REDUCE pass from
 # level 0 and from levels >= 1, of the up passes that evaluate the product-sum
@@ -151,6 +151,8 @@ def lib() -> ctypes.CDLL:
         L.fourier_llf_server_destroy.restype = None
         L.fourier_llf_reparam.argtypes = [vp, jp, jp, vp, sz, vp]
         L.fourier_llf_reparam.restype = i32
+        L.fourier_llf_run_static.argtypes = [vp, jp, vp]
+        L.fourier_llf_run_static.restype = i32
         _LIB = L
     return _LIB
 
@@ -405,6 +407,19 @@ class FourierLLF:
         tensor when None; any view with contiguous rows otherwise); returns it."""
         fj, out = self._prepare(Job(x, levels, sigma_r, m, K, R, T, out, m_map, sigma_map, sigma_max))
         self.run_jobs([fj], stream=stream, keep=(out, m_map, sigma_map))
+        return out
+
+    def run_static(self, x, levels: int, sigma_r: float, m: float, K: int, R: float = 1.0, T: float = 0.0,
+                   out=None, m_map=None, stream=None, sigma_map=None, sigma_max: float = 0.0):
+        """Like run, through fourier_llf_run_static: the workspace is the library's
+        static device array (no workspace tensor is allocated).  `out` should be
+        given by callers that must not allocate."""
+        import torch
+        fj, out = self._prepare(Job(x, levels, sigma_r, m, K, R, T, out, m_map, sigma_map, sigma_max))
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().fourier_llf_run_static(self._ctx, ctypes.byref(fj), sptr), self._ctx)
         return out
 
     def run_batch(self, jobs: Sequence[Job], stream=None) -> List["object"]:
