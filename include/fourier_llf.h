@@ -292,6 +292,21 @@ fllf_status fourier_llf_server_stats(const fllf_server *srv, fllf_server_stats *
 /* Release the server.  NULL-safe; waits for the work it enqueued. */
 void fourier_llf_server_destroy(fllf_server *srv);
 
+/* ---- boost map from local variance --------------------------------------- */
+
+/* Boost map of the variance-driven pixel-by-pixel enhancement (Sec. IV: the
+ * enhancement of a pixel follows the variance of the pixels in a local window,
+ * small where the variance is low):
+ *   out[y][x] = m_max v / (v + v_half),
+ * v the population variance of `in` over the (2 radius + 1)^2 window around
+ * (x, y) with reflect-101 borders.  in: device, height x width float32 with
+ * row pitch row_pitch (0 = width; e.g. one channel of a job's input); out:
+ * device, dense height x width float32, usable as fllf_job.m_map; in and out
+ * must not overlap.  radius in [0, 32], m_max finite, v_half > 0; the size
+ * limits of fllf_job apply.  Asynchronous on hip_stream; ctx names the device. */
+fllf_status fourier_llf_boost_map(fllf_ctx *ctx, const float *in, int32_t width, int32_t height, int64_t row_pitch,
+                                  int32_t radius, double m_max, double v_half, float *out, void *hip_stream);
+
 /* ---- kernel timing (benchmarks) ------------------------------------------ */
 
 /* Aggregated device time of one kernel class over the launches recorded since
@@ -326,6 +341,13 @@ fllf_status fourier_llf_timing_read(fllf_ctx *ctx, fllf_kernel_time *out, int ma
  * either may be NULL). */
 fllf_status fourier_llf_fit(double sigma_r, int K, double range_R, double T_in, double *T_out,
                             double *omega, double *alpha_tilde);
+
+/* One period T for every range scale in [sigma_lo, sigma_hi] (pixel-by-pixel
+ * alpha~_{k,p}, Sec. III-B: the Fourier pyramids depend on T, so all pixels share
+ * it): T = argmin_{T > R} erfc(pi sigma_lo (2K+1)/T) + erfc((T-R)/sigma_hi), each
+ * term of Eq. (12) at the scale where it is largest; with sigma_lo = sigma_hi it
+ * is fourier_llf_fit's T.  The period a job with a sigma_map uses. */
+fllf_status fourier_llf_fit_range(double sigma_lo, double sigma_hi, int K, double range_R, double *T_out);
 
 /* Largest valid level count for an image: 1 + floor(log2(min(height, width))),
  * capped at FLLF_MAX_LEVELS; 0 for non-positive sizes. */

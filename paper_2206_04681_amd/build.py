@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfourier_llf.so")
 ARCH = "gfx950"
 
-SOURCES = ["fllf_host.cpp", "fllf_server.cpp", "fllf_batch.hip", "fllf_static.hip", "fllf_kernels_f32.hip",
+SOURCES = ["fllf_host.cpp", "fllf_server.cpp", "fllf_batch.hip", "fllf_static.hip", "fllf_boostmap.hip", "fllf_kernels_f32.hip",
            "fllf_kernels_f16.hip", "fllf_kernels_bf16.hip"]
 
 # Packed FP32 instructions are disabled for all device code on this target.

@@ -101,7 +101,8 @@ void add_launches(const PassItem *items, int n, int dwp, char *ws, const Tuning 
     if (!it.down && it.l >= 1 && fuse)  // the collapse: one kernel for every job
       groups[Key(1, false, 0, false, false, false, true)].push_back(i);
     else
-      groups[Key(it.down ? 0 : 1, it.l == 0, km, ex, it.P->m_map != nullptr, hasd, fuse)].push_back(i);
+      groups[Key(it.down ? 0 : 1, it.l == 0, km, ex, it.P->m_map != nullptr || it.P->s_map != nullptr, hasd, fuse)]
+          .push_back(i);
   }
   for (auto &kv : groups) {
     const std::vector<int> &is = kv.second;

@@ -117,6 +117,9 @@ namespace fllf {
 // which has no underflow even where both erfc terms are below 1e-300.  The
 // minimum is the first crossing of F from negative to positive; it is bracketed
 // on a uniform grid and refined by bisection to full double precision.
+// With a range of scales [s_lo, s_hi] (one T for every pixel, Sec. III-B) the
+// truncation term is taken at s_lo (a = pi s_lo (2K + 1)) and the aliasing term
+// at s_hi (s = s_hi): each at the scale where it is largest.
 // ---------------------------------------------------------------------------
 static double stationarity(double T, double a, double s, double R) {
   return std::log(a * s / (T * T)) - (a * a) / (T * T) + (T - R) * (T - R) / (s * s);
@@ -126,8 +129,7 @@ static double period_error(double T, double a, double s, double R) {
   return std::erfc(a / T) + std::erfc((T - R) / s);
 }
 
-double fit_period(double s, int K, double R) {
-  const double a = M_PI * s * (2.0 * K + 1.0);
+static double fit_period_as(double a, double s, double R) {
   const double lo = R, hi = R + 20.0 * s + 4.0 * a;
   const int n = 4096;
   double prev_T = lo + (hi - lo) / n, prev_F = stationarity(prev_T, a, s, R);
@@ -153,6 +155,12 @@ double fit_period(double s, int K, double R) {
     if (E < best_E) { best_E = E; best_T = T; }
   }
   return best_T;
+}
+
+double fit_period(double s, int K, double R) { return fit_period_as(M_PI * s * (2.0 * K + 1.0), s, R); }
+
+double fit_period_range(double s_lo, double s_hi, int K, double R) {
+  return fit_period_as(M_PI * s_lo * (2.0 * K + 1.0), s_hi, R);
 }
 
 // omega_k = 2 pi k / T; alpha_k = s sqrt(2 pi) / T exp(-(omega_k s)^2 / 2) (Eq. (9));
@@ -181,6 +189,7 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
   p->in = job.in;
   p->out = job.out;
   p->m_map = job.m_map;
+  p->s_map = job.sigma_map;
   const size_t pair_bytes = 2 * (size_t)storage_bytes(storage);
   int w = job.width, h = job.height;
   size_t off = base;
@@ -207,6 +216,10 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
           L.off_m = off;
           off += g_plane;
         }
+        if (job.sigma_map) {
+          L.off_s = off;
+          off += g_plane;
+        }
       }
     }
     w = (w + 1) / 2;
@@ -227,13 +240,19 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
   cp.dstride = p->out_cs * sizeof(float);
   cp.C = job.channels;
 
-  const double T = job.period_T > 0.0 ? job.period_T : fit_period(job.sigma_r, job.K, job.range_R);
+  const double T = job.period_T > 0.0 ? job.period_T
+                   : job.sigma_map  ? fit_period_range(job.sigma_r, job.sigma_max, job.K, job.range_R)
+                                    : fit_period(job.sigma_r, job.K, job.range_R);
   double at[kMaxK];
   fourier_terms(job.sigma_r, job.K, T, nullptr, at);
   p->coefs.inv_T = (float)(1.0 / T);
   p->coefs.m = (float)job.m;
   p->coefs.K = job.K;
-  p->coefs.has_map = job.m_map ? 1 : 0;
+  p->coefs.has_mmap = job.m_map ? 1 : 0;
+  p->coefs.has_smap = job.sigma_map ? 1 : 0;
+  p->coefs.sref = (float)job.sigma_r;
+  p->coefs.inv_sref = (float)(1.0 / job.sigma_r);
+  p->coefs.qk = (float)(0.5 * (2.0 * M_PI / T) * (2.0 * M_PI / T));
   for (int k = 0; k < kMaxK; ++k) {
     p->coefs.at[k] = k < job.K ? (float)at[k] : 0.0f;
     p->coefs.wt[k] = 1.0f;
@@ -368,11 +387,8 @@ static fllf_status validate(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_sto
       return fail(ctx, FLLF_EINVAL, "job %d: m_map and out overlap", i);
     if (fllf::spans_overlap(j.sigma_map, fllf::map_span(j), j.out, fllf::out_span(j)))
       return fail(ctx, FLLF_EINVAL, "job %d: sigma_map and out overlap", i);
-    if (j.sigma_map) {
-      if (!is_finite(j.sigma_max) || j.sigma_max < j.sigma_r)
-        return fail(ctx, FLLF_EINVAL, "job %d: with sigma_map, sigma_max must be finite and >= sigma_r", i);
-      return fail(ctx, FLLF_EUNSUPPORTED, "job %d: sigma_map is not supported", i);
-    }
+    if (j.sigma_map && (!is_finite(j.sigma_max) || j.sigma_max < j.sigma_r))
+      return fail(ctx, FLLF_EINVAL, "job %d: with sigma_map, sigma_max must be finite and >= sigma_r", i);
   }
   // in a batch every output must be disjoint from every other job's images
   for (int i = 0; i < n && n > 1; ++i) {
@@ -429,6 +445,15 @@ fllf_status fourier_llf_fit(double sigma_r, int K, double range_R, double T_in, 
   const double T = T_in > 0.0 ? T_in : fllf::fit_period(sigma_r, K, range_R);
   if (T_out) *T_out = T;
   fllf::fourier_terms(sigma_r, K, T, omega, alpha_tilde);
+  return FLLF_OK;
+}
+
+fllf_status fourier_llf_fit_range(double sigma_lo, double sigma_hi, int K, double range_R, double *T_out) {
+  if (!T_out || !is_finite(sigma_lo) || sigma_lo <= 0.0 || !is_finite(sigma_hi) || sigma_hi < sigma_lo || K < 1 ||
+      K > FLLF_MAX_K || !is_finite(range_R) || range_R <= 0.0)
+    return fail(nullptr, FLLF_EINVAL, "fit_range: need 0 < sigma_lo <= sigma_hi, 1 <= K <= %d, R > 0, T_out",
+                FLLF_MAX_K);
+  *T_out = fllf::fit_period_range(sigma_lo, sigma_hi, K, range_R);
   return FLLF_OK;
 }
 
@@ -681,7 +706,8 @@ fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_
   if (a.in != b.in || a.width != b.width || a.height != b.height || a.channels != b.channels ||
       a.levels != b.levels || a.K != b.K || a.range_R != b.range_R)
     return fail(ctx, FLLF_EINVAL, "reparam: input, size, channels, levels, K and R must match the resident job");
-  if (a.m_map || b.m_map) return fail(ctx, FLLF_EUNSUPPORTED, "reparam: boost maps are not supported");
+  if (a.m_map || b.m_map || a.sigma_map || b.sigma_map)
+    return fail(ctx, FLLF_EUNSUPPORTED, "reparam: per-pixel maps are not supported");
   if (b.K != 4 && b.K != 8 && b.K != 16) return fail(ctx, FLLF_EUNSUPPORTED, "reparam: K must be 4, 8 or 16");
   const double T = a.period_T > 0.0 ? a.period_T : fllf::fit_period(a.sigma_r, a.K, a.range_R);
   if (b.period_T != 0.0 && b.period_T != T)

@@ -21,11 +21,19 @@ inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a
 // Coefficients of the Fourier remap (Eq. (11)) in the form the kernels use:
 // angle of term k at intensity v is 2 pi k (v * inv_T); the product-sum weight of
 // term k is boost * at[k] where at[k] = alpha~_{k+1} (Eq. (11)).
+//
+// Pixel-by-pixel range scale (Sec. III-B): at[k] is alpha~_k at the reference
+// scale sref (the smallest in the map), and a pixel of scale s weighs term k by
+//   alpha~_k(s) / alpha~_k(sref) = (s / sref)^3 Q^(k^2),
+//   Q = exp(-qk (s^2 - sref^2)),  qk = (2 pi / T)^2 / 2           (Eq. (9), (11)),
+// which is 1 for every k at s = sref.
 struct Coefs {
   float inv_T;
   float m;          // scalar boost (used when the job has no m_map)
   int K;
-  int has_map;      // 1: per-pixel boost read from the level's m plane
+  int has_mmap;     // 1: per-pixel boost read from the level's m plane
+  int has_smap;     // 1: per-pixel range scale read from the level's sigma plane
+  float sref, inv_sref, qk;
   float at[kMaxK];  // alpha~_1 .. alpha~_K
   float wt[kMaxK];  // re-parameterisation: new / resident alpha~_k (1 otherwise)
 };
@@ -41,6 +49,7 @@ struct Level {
   size_t off_cs;     // (C~, S~)_{l,k}    storage pair, channels x K x plane
   size_t off_o;      // O_l (collapse)    float32, channels x plane   (1 <= l < top)
   size_t off_m;      // G_l[m_map]        float32, one plane           (1 <= l < top)
+  size_t off_s;      // G_l[sigma_map]    float32, one plane           (1 <= l < top)
   size_t g_cstride;  // elements between channels of G and O
   size_t cs_kstride; // pair elements between consecutive k (1: the K pairs of a pixel are contiguous)
   size_t cs_cstride; // pair elements between channels
@@ -65,6 +74,7 @@ struct JobPlan {
   const float *in;
   float *out;
   const float *m_map;
+  const float *s_map;  // per-pixel range scales (sigma_map) or null
   // level-0 images: element pitches of the caller's rows and channels (the
   // input's row pitch is also lv[0].pitch); the maps have dense rows
   size_t in_cs, out_cs;
@@ -95,6 +105,9 @@ inline bool spans_overlap(const void *p, size_t a, const void *q, size_t b) {
 
 // Host fit in float64 (Eq. (9)-(12)).
 double fit_period(double sigma_r, int K, double R);
+// One period for range scales in [sigma_lo, sigma_hi]: Eq. (12) with its
+// truncation term at sigma_lo and its aliasing term at sigma_hi.
+double fit_period_range(double sigma_lo, double sigma_hi, int K, double R);
 void fourier_terms(double sigma_r, int K, double T, double *omega, double *alpha_tilde);
 
 // Plans one job: level sizes and workspace offsets starting at byte `base`.

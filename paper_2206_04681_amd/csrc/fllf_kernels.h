@@ -290,6 +290,26 @@ struct Harmonics {
   }
 };
 
+// Pixel-by-pixel range scale (Sec. III-B): the factor alpha~_k(s) / alpha~_k(sref)
+// = rho^3 Q^(k^2) of a pixel of scale s (see Coefs), for k = 1, 2, ... by the
+// recurrence Q^((k+1)^2) = Q^(k^2) Q^(2k+1), Q^(2k+3) = Q^(2k+1) Q^2; rho^3 is
+// applied once to the sum over k.  At s = sref every factor is exactly 1.
+struct TermScale {
+  float e, r, q2, r3;  // Q^(k^2), Q^(2k+1), Q^2, rho^3
+  __device__ inline void init(float s, const Coefs &cf) {
+    const float q = expf(-cf.qk * (s * s - cf.sref * cf.sref));
+    e = q;
+    q2 = q * q;
+    r = q2 * q;
+    const float rho = s * cf.inv_sref;
+    r3 = cf.has_smap ? rho * rho * rho : 1.f;
+  }
+  __device__ inline void next() {
+    e *= r;
+    r *= q2;
+  }
+};
+
 // Unnormalised horizontal REDUCE at the lane's even fine column 2j from its
 // samples v0 (2j), v1 (2j+1) and its neighbours': taps [1 4 6 4 1].
 // Each lane shift feeds exactly one add (folded into a DPP add), and the result
@@ -340,6 +360,9 @@ __device__ inline void vstep(float h, float &P0, float &P1, float &out) {
 // Minimum waves per SIMD a kernel is compiled for: 2 (<= 256 VGPRs) up to 8
 // terms; with 16 or 32 terms the pyramid rows need the whole register file.
 constexpr int min_waves_per_simd(int KM) { return KM <= 8 ? 2 : 1; }
+// The fused down pass with per-pixel maps carries the maps' ring as well: one
+// wave per SIMD, so that it keeps its state in registers.
+constexpr int down_waves_per_simd(int KM, bool MAP, bool FUSE) { return MAP && FUSE ? 1 : min_waves_per_simd(KM); }
 
 
 // --------------------------------------------------------------------------
@@ -359,9 +382,11 @@ struct DownArgs {
   const float *gf; size_t gf_cs;         // G_l (the input I at level 0)
   const uint32_t *csf; size_t csf_cs;    // level-l pair records (l >= 1), dwords per channel
   const float *mf;                       // level-l boost plane (m_map at level 0)
+  const float *sf;                       // level-l range-scale plane (sigma_map at level 0)
   float *gc; size_t gc_cs;               // G_{l+1}
   uint32_t *csc; size_t csc_cs;          // level-(l+1) pair records
   float *mc;                             // level-(l+1) boost plane or null
+  float *sc;                             // level-(l+1) range-scale plane or null
   float *af; size_t af_cs;               // A_l (l >= 1), stored in the O_l slot
   int minus_g;                           // fused level 1: store L_1[O] - G_1 (see UpArgs::oc_minus_g)
   Geom g;
@@ -372,6 +397,7 @@ struct UpArgs {
   const float *base; size_t base_cs;     // A_l, or I at level 0 (may alias out)
   const float *gf; size_t gf_cs;         // G_l, or I at level 0
   const float *mf;                       // level-l boost plane, or m_map at level 0
+  const float *sf;                       // level-l range-scale plane, or sigma_map at level 0
   const float *gc; size_t gc_cs;         // G_{l+1}
   const float *oc; size_t oc_cs;         // O_{l+1} (null when l+1 is the top level)
   const uint32_t *csc; size_t csc_cs;    // level-(l+1) pair records
@@ -438,7 +464,7 @@ __device__ inline bool border_strip(int strip, int Wf, int sw = 62, int hl = 1) 
 template <int KM>
 struct FuseRing {
   float Gm, G0, Gp, Cm[KM], C0[KM], Cp[KM], Sm[KM], S0[KM], Sp[KM];
-  float pA[4][2], pc[4][2], ps[4][2], pm[4][2];
+  float pA[4][2], pc[4][2], ps[4][2], pm[4][2], pq[4][2];  // pq: range scale (maps only)
 };
 struct NoRing {};
 
@@ -453,7 +479,7 @@ struct DownWave {
   static constexpr int DW = PS::DW;
   static constexpr int NR = KM * DW;  // dwords of a full record
   struct RowIn {  // one fine row as loaded (raw), for the one-row-ahead prefetch
-    float g0, g1, m0, m1;
+    float g0, g1, m0, m1, s0, s1;  // G (or I), boost, range scale at the two columns
     uint32_t q[2 * NR];  // records of fine columns x0 and x0 + 1
   };
   // With exact K the coarse records are written through LDS (whole lines per
@@ -477,7 +503,7 @@ struct DownWave {
   uint32_t *slice;                                     // this wave's LDS staging slice
   const float *gf;
   const uint32_t *csf;
-  float PG0, PG1, PM0, PM1;
+  float PG0, PG1, PM0, PM1, PQ0, PQ1;
   float PC0[KM], PC1[KM], PS0[KM], PS1[KM];
   typename std::conditional<FUSE, FuseRing<KM>, NoRing>::type z;
 
@@ -505,7 +531,7 @@ struct DownWave {
       for (int k = 0; k < KM; ++k) z.Cm[k] = z.C0[k] = z.Cp[k] = z.Sm[k] = z.S0[k] = z.Sp[k] = 0.f;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        for (int e = 0; e < 2; ++e) z.pA[q][e] = z.pc[q][e] = z.ps[q][e] = z.pm[q][e] = 0.f;
+        for (int e = 0; e < 2; ++e) z.pA[q][e] = z.pc[q][e] = z.ps[q][e] = z.pm[q][e] = z.pq[q][e] = 0.f;
     }
     const int f0 = reflect(x0, a.g.Wf), f1 = reflect(x0 + 1, a.g.Wf);
     vx = (uint32_t)max(x0, 0) * 4u;
@@ -538,7 +564,13 @@ struct DownWave {
   __device__ inline void load(RowIn &d, int r) const {
     const uint32_t fr = (uint32_t)reflect(r, a.g.Hf);
     ld_f2<BORDER>(Plane(gf), fr * (uint32_t)a.g.pf * 4u, d.g0, d.g1);
-    if (MAP) ld_f2<BORDER>(Plane(a.mf), fr * (uint32_t)a.g.pm * 4u, d.m0, d.m1);
+    if (MAP) {  // either map may be absent (wave-uniform): its scalar then
+      const uint32_t sm = fr * (uint32_t)a.g.pm * 4u;
+      if (a.mf) ld_f2<BORDER>(Plane(a.mf), sm, d.m0, d.m1);
+      else d.m0 = d.m1 = a.cf.m;
+      if (a.sf) ld_f2<BORDER>(Plane(a.sf), sm, d.s0, d.s1);
+      else d.s0 = d.s1 = a.cf.sref;
+    }
     if (!L0) {
       const Plane p(csf);
       const uint32_t so = fr * (uint32_t)a.g.pf * rec;
@@ -567,7 +599,9 @@ struct DownWave {
     float og = 0.f, om = 0.f;
     float oc[KM], os[KM];
     vstep<ROLE>(hred(d.g0, d.g1), PG0, PG1, og);
+    float oq = 0.f;
     if (MAP) vstep<ROLE>(hred(d.m0, d.m1), PM0, PM1, om);
+    if (MAP) vstep<ROLE>(hred(d.s0, d.s1), PQ0, PQ1, oq);
     if (L0) {
       float s, cc;
       sincos2pi(d.g0 * a.cf.inv_T, s, cc);
@@ -608,16 +642,32 @@ struct DownWave {
       Harmonics h1;
       h1.init(c1, s1);
       float acc0 = 0.f, acc1 = 0.f;
+      TermScale t0, t1;
+      if (MAP) {
+        t0.init(d.s0, a.cf);
+        t1.init(d.s1, a.cf);
+      }
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         if (EX || k < K) {
           const float2 q0 = PS::cvt(&d.q[k * DW]), q1 = PS::cvt(&d.q[NR + k * DW]);
-          // pairs carry at_k
-          acc0 = fmaf(h0.s, q0.x, fmaf(-h0.c, q0.y, acc0));
-          acc1 = fmaf(h1.s, q1.x, fmaf(-h1.c, q1.y, acc1));
+          // pairs carry at_k; with maps, each term takes the pixel's factor
+          if (MAP) {
+            acc0 = fmaf(t0.e, fmaf(h0.s, q0.x, -h0.c * q0.y), acc0);
+            acc1 = fmaf(t1.e, fmaf(h1.s, q1.x, -h1.c * q1.y), acc1);
+            t0.next();
+            t1.next();
+          } else {
+            acc0 = fmaf(h0.s, q0.x, fmaf(-h0.c, q0.y, acc0));
+            acc1 = fmaf(h1.s, q1.x, fmaf(-h1.c, q1.y, acc1));
+          }
           h0.next();
           h1.next();
         }
+      }
+      if (MAP) {
+        acc0 *= t0.r3;
+        acc1 *= t1.r3;
       }
       // with minus_g (fused level 1) the pass leaves L_1[O] - G_1, whose collapse
       // is the O_1 - G_1 that up(0) expands: it then need not read G_1
@@ -636,12 +686,14 @@ struct DownWave {
       z.pc[3][0] = c0; z.pc[3][1] = c1;
       z.ps[3][0] = s0; z.ps[3][1] = s1;
       z.pm[3][0] = m0; z.pm[3][1] = m1;
+      if (MAP) { z.pq[3][0] = d.s0; z.pq[3][1] = d.s1; }
     }
     if (ROLE == 4 && ci >= i0 && (!FUSE || ci < i1)) {  // wave-uniform
       const uint32_t so = (uint32_t)ci * (uint32_t)a.g.pc;
       if (writer) {
         Plane(a.gc + (size_t)c * a.gc_cs).st1(og, vcj, so * 4u);
         if (MAP && a.mc && c == 0) Plane(a.mc).st1(om, vcj, so * 4u);
+        if (MAP && a.sc && c == 0) Plane(a.sc).st1(oq, vcj, so * 4u);
       }
       uint32_t q[NR];
 #pragma unroll
@@ -682,11 +734,13 @@ struct DownWave {
         z.pc[0][e] = z.pc[2][e]; z.pc[1][e] = z.pc[3][e];
         z.ps[0][e] = z.ps[2][e]; z.ps[1][e] = z.ps[3][e];
         z.pm[0][e] = z.pm[2][e]; z.pm[1][e] = z.pm[3][e];
+        if (MAP) { z.pq[0][e] = z.pq[2][e]; z.pq[1][e] = z.pq[3][e]; }
       }
       z.pA[2][0] = A0; z.pA[2][1] = A1;
       z.pc[2][0] = c0; z.pc[2][1] = c1;
       z.ps[2][0] = s0; z.ps[2][1] = s1;
       z.pm[2][0] = m0; z.pm[2][1] = m1;
+      if (MAP) { z.pq[2][0] = d.s0; z.pq[2][1] = d.s1; }
     }
   }
 
@@ -698,10 +752,12 @@ struct DownWave {
     float EG[4];
     expand4(z.Gm, z.G0, z.Gp, EG);
     Harmonics hm[4];
+    TermScale ts[4];
     float acc[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       hm[p].init(z.pc[p >> 1][p & 1], z.ps[p >> 1][p & 1]);
+      if (MAP) ts[p].init(z.pq[p >> 1][p & 1], a.cf);
       acc[p] = 0.f;
     }
 #pragma unroll
@@ -712,10 +768,19 @@ struct DownWave {
         expand4(z.Sm[k], z.S0[k], z.Sp[k], ES);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-          acc[p] = fmaf(hm[p].s, EC[p], fmaf(-hm[p].c, ES[p], acc[p]));
+          if (MAP) {
+            acc[p] = fmaf(ts[p].e, fmaf(hm[p].s, EC[p], -hm[p].c * ES[p]), acc[p]);
+            ts[p].next();
+          } else {
+            acc[p] = fmaf(hm[p].s, EC[p], fmaf(-hm[p].c, ES[p], acc[p]));
+          }
           hm[p].next();
         }
       }
+    }
+    if (MAP) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) acc[p] *= ts[p].r3;
     }
     // EXPAND weights (1 6 1)/8 and (1 1)/2 per axis, by the block position
     const float scl[4] = {1.f / 64.f, 1.f / 16.f, 1.f / 16.f, 1.f / 4.f};
@@ -769,7 +834,7 @@ struct DownWave {
 };
 
 template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE>
-__global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownArgs a) {
+__global__ void __launch_bounds__(256, down_waves_per_simd(KM, MAP, FUSE)) down_kernel(DownArgs a) {
   using W = DownWave<ST, KM, EX, L0, MAP, FUSE>;
   constexpr int SLICE = W::SLICE;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * SLICE];
@@ -780,7 +845,7 @@ __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) down_kernel(DownA
 }
 
 template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE>
-__global__ void __launch_bounds__(256, min_waves_per_simd(KM))
+__global__ void __launch_bounds__(256, down_waves_per_simd(KM, MAP, FUSE))
 down_batch_kernel(const DownArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n,
                   uint32_t total) {
   using W = DownWave<ST, KM, EX, L0, MAP, FUSE>;
@@ -938,8 +1003,8 @@ struct UpWave {
     int par;                // FOLD: parity of the level-1 row ci
     uint32_t q[NR];
   };
-  struct FBlk {  // fine 2x2 block as loaded: G (or I), A (or I), boost
-    float g[4], b[4], m[4];
+  struct FBlk {  // fine 2x2 block as loaded: G (or I), A (or I), boost, range scale
+    float g[4], b[4], m[4], s[4];
   };
   // interior strips read each coarse row of records as one coalesced span
   static constexpr bool SPAN = EX;
@@ -1069,7 +1134,13 @@ struct UpWave {
       const uint32_t so = rr[q] * (uint32_t)a.g.pf * 4u;
       ld_f2<BORDER>(Plane(gfp), so, d.g[2 * q], d.g[2 * q + 1]);
       if (!L0) ld_f2<BORDER>(Plane(base), so, d.b[2 * q], d.b[2 * q + 1]);
-      if (MAP) ld_f2<BORDER>(Plane(a.mf), rr[q] * (uint32_t)a.g.pm * 4u, d.m[2 * q], d.m[2 * q + 1]);
+      if (MAP) {  // either map may be absent (wave-uniform): its scalar then
+        const uint32_t sm = rr[q] * (uint32_t)a.g.pm * 4u;
+        if (a.mf) ld_f2<BORDER>(Plane(a.mf), sm, d.m[2 * q], d.m[2 * q + 1]);
+        else d.m[2 * q] = d.m[2 * q + 1] = a.cf.m;
+        if (a.sf) ld_f2<BORDER>(Plane(a.sf), sm, d.s[2 * q], d.s[2 * q + 1]);
+        else d.s[2 * q] = d.s[2 * q + 1] = a.cf.sref;
+      }
     }
   }
 
@@ -1112,12 +1183,14 @@ struct UpWave {
       float ED[4] = {0.f, 0.f, 0.f, 0.f};
       if (HASD) expand4(Dm, D0, Dp, ED);
       Harmonics hm[4];
+      TermScale ts[4];
       float acc[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         float s, cc;
         sincos2pi(fa.g[p] * a.cf.inv_T, s, cc);
         hm[p].init(cc, s);
+        if (MAP) ts[p].init(fa.s[p], a.cf);
         acc[p] = 0.f;
       }
 #pragma unroll
@@ -1129,7 +1202,12 @@ struct UpWave {
           expand4(Sm[k], S0[k], v.y, ES);
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
-            acc[p] = fmaf(hm[p].s, EC[p], fmaf(-hm[p].c, ES[p], acc[p]));
+            if (MAP) {
+              acc[p] = fmaf(ts[p].e, fmaf(hm[p].s, EC[p], -hm[p].c * ES[p]), acc[p]);
+              ts[p].next();
+            } else {
+              acc[p] = fmaf(hm[p].s, EC[p], fmaf(-hm[p].c, ES[p], acc[p]));
+            }
             hm[p].next();
           }
           Cm[k] = C0[k];
@@ -1137,6 +1215,10 @@ struct UpWave {
           Sm[k] = S0[k];
           S0[k] = v.y;
         }
+      }
+      if (MAP) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) acc[p] *= ts[p].r3;
       }
       // EXPAND weights (1 6 1)/8 and (1 1)/2 per axis, by the block position
       const float scl[4] = {1.f / 64.f, 1.f / 16.f, 1.f / 16.f, 1.f / 4.f};
@@ -1341,23 +1423,26 @@ inline dim3 grid_for(const Geom &g) {
 inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const Tuning &tu) {
   const Level *lv = P.lv;
   const int L = P.levels;
-  const bool map = P.m_map != nullptr;
-  auto M = [&](int k) -> float * {
-    if (!map) return nullptr;
-    if (k == 0) return const_cast<float *>(P.m_map);
-    return k < L - 1 ? (float *)(ws + lv[k].off_m) : nullptr;
+  // the Gaussian pyramid of a per-pixel map: the caller's map at level 0, the
+  // workspace plane at levels 1 .. top-1 (the top level has no product-sum)
+  auto M = [&](const float *map0, size_t Level::*off, int k) -> float * {
+    if (!map0) return nullptr;
+    if (k == 0) return const_cast<float *>(map0);
+    return k < L - 1 ? (float *)(ws + lv[k].*off) : nullptr;
   };
   DownArgs a{};
   a.gf = l == 0 ? P.in : (const float *)(ws + lv[l].off_g);
   a.gf_cs = l == 0 ? P.in_cs : lv[l].g_cstride;
   a.csf = l == 0 ? nullptr : (const uint32_t *)(ws + lv[l].off_cs);
   a.csf_cs = lv[l].cs_cstride * dwp;
-  a.mf = M(l);
+  a.mf = M(P.m_map, &Level::off_m, l);
+  a.sf = M(P.s_map, &Level::off_s, l);
   a.gc = (float *)(ws + lv[l + 1].off_g);
   a.gc_cs = lv[l + 1].g_cstride;
   a.csc = (uint32_t *)(ws + lv[l + 1].off_cs);
   a.csc_cs = lv[l + 1].cs_cstride * dwp;
-  a.mc = M(l + 1);
+  a.mc = M(P.m_map, &Level::off_m, l + 1);
+  a.sc = M(P.s_map, &Level::off_s, l + 1);
   a.af = l == 0 ? nullptr : (float *)(ws + lv[l].off_o);
   a.af_cs = lv[l].g_cstride;
   a.minus_g = l == 1 && fused_level(P, 1) && L > 2 ? 1 : 0;
@@ -1370,13 +1455,13 @@ inline DownArgs make_down_args(const JobPlan &P, int l, char *ws, int dwp, const
 inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tuning &tu, bool reparam = false) {
   const Level *lv = P.lv;
   const int L = P.levels;
-  const bool map = P.m_map != nullptr;
   UpArgs a{};
   a.base = l == 0 ? P.in : (const float *)(ws + lv[l].off_o);
   a.base_cs = l == 0 ? P.in_cs : lv[l].g_cstride;
   a.gf = l == 0 ? P.in : (const float *)(ws + lv[l].off_g);
   a.gf_cs = l == 0 ? P.in_cs : lv[l].g_cstride;
-  a.mf = !map ? nullptr : l == 0 ? P.m_map : (const float *)(ws + lv[l].off_m);
+  a.mf = !P.m_map ? nullptr : l == 0 ? P.m_map : (const float *)(ws + lv[l].off_m);
+  a.sf = !P.s_map ? nullptr : l == 0 ? P.s_map : (const float *)(ws + lv[l].off_s);
   a.gc = (const float *)(ws + lv[l + 1].off_g);
   a.gc_cs = lv[l + 1].g_cstride;
   const bool hasd = l + 1 < L - 1;
@@ -1408,14 +1493,14 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
 // Algorithmic bytes: every plane element a launch must read or write, once.
 inline double down_bytes(const JobPlan &P, int l, int dwp) {
   const Level *lv = P.lv;
-  const double pb = 4.0 * dwp * P.K, C = P.C, mapb = P.m_map ? 4.0 : 0.0;
+  const double pb = 4.0 * dwp * P.K, C = P.C, mapb = (P.m_map ? 4.0 : 0.0) + (P.s_map ? 4.0 : 0.0);
   if (l == 0) return C * (4.0 * lv[0].n + (4.0 + pb) * lv[1].n) + mapb * (lv[0].n + lv[1].n);
   return C * ((4.0 + pb + 4.0) * lv[l].n + (4.0 + pb) * lv[l + 1].n) + mapb * (lv[l].n + lv[l + 1].n);
 }
 
 inline double up_bytes(const JobPlan &P, int l, int dwp, bool reparam = false) {
   const Level *lv = P.lv;
-  const double pb = 4.0 * dwp * P.K, C = P.C, mapb = P.m_map ? 4.0 : 0.0;
+  const double pb = 4.0 * dwp * P.K, C = P.C, mapb = (P.m_map ? 4.0 : 0.0) + (P.s_map ? 4.0 : 0.0);
   const bool hasd = l + 1 < P.levels - 1;
   if (!reparam && fused_level(P, l)) return C * (8.0 * lv[l].n + 4.0 * lv[l + 1].n);  // L_l, O_l; O_{l+1}
   const bool fold = l == 0 && hasd && !reparam && fused_level(P, 1);  // L_1[O] - G_1, and O_2
@@ -1487,7 +1572,7 @@ inline void k_class(int K, int *km, bool *ex) {
 
 template <int ST>
 hipError_t launch_storage(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *h, const Tuning &tu) {
-  const bool map = P.m_map != nullptr;
+  const bool map = P.m_map != nullptr || P.s_map != nullptr;  // per-pixel parameters
   int km;
   bool ex;
   k_class(P.K, &km, &ex);

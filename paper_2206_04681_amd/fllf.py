@@ -31,7 +31,8 @@ EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run
             "fourier_llf_graph_create", "fourier_llf_graph_launch", "fourier_llf_graph_destroy",
             "fourier_llf_server_create", "fourier_llf_server_submit", "fourier_llf_server_step",
             "fourier_llf_server_poll", "fourier_llf_server_stats", "fourier_llf_server_destroy",
-            "fourier_llf_reparam", "fourier_llf_run_static")
+            "fourier_llf_reparam", "fourier_llf_run_static", "fourier_llf_fit_range",
+            "fourier_llf_boost_map")
 
 # Launch-shape parameters (FLLF_TUNE_*): target waves of the REDUCE pass from
 # level 0 and from levels >= 1, of the up passes that evaluate the product-sum
@@ -153,6 +154,10 @@ def lib() -> ctypes.CDLL:
         L.fourier_llf_reparam.restype = i32
         L.fourier_llf_run_static.argtypes = [vp, jp, vp]
         L.fourier_llf_run_static.restype = i32
+        L.fourier_llf_fit_range.argtypes = [dbl, dbl, i32, dbl, dp]
+        L.fourier_llf_fit_range.restype = i32
+        L.fourier_llf_boost_map.argtypes = [vp, vp, i32, i32, ctypes.c_int64, i32, dbl, dbl, vp, vp]
+        L.fourier_llf_boost_map.restype = i32
         _LIB = L
     return _LIB
 
@@ -174,6 +179,13 @@ def fit(sigma_r: float, K: int, R: float = 1.0, T: float = 0.0) -> Tuple[float, 
     at = (ctypes.c_double * max(K, 1))()
     _check(lib().fourier_llf_fit(float(sigma_r), int(K), float(R), float(T), ctypes.byref(Tout), om, at))
     return Tout.value, np.array(om[:K]), np.array(at[:K])
+
+
+def fit_range(sigma_lo: float, sigma_hi: float, K: int, R: float = 1.0) -> float:
+    """Host float64 period shared by the range scales [sigma_lo, sigma_hi]."""
+    T = ctypes.c_double()
+    _check(lib().fourier_llf_fit_range(float(sigma_lo), float(sigma_hi), int(K), float(R), ctypes.byref(T)))
+    return T.value
 
 
 def max_levels(height: int, width: int) -> int:
@@ -420,6 +432,26 @@ class FourierLLF:
             stream = torch.cuda.current_stream(self.device)
         sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         _check(lib().fourier_llf_run_static(self._ctx, ctypes.byref(fj), sptr), self._ctx)
+        return out
+
+    def boost_map(self, plane, radius: int, m_max: float, v_half: float, out=None, stream=None):
+        """Variance-driven boost map of one (H, W) float32 CUDA plane (rows
+        contiguous; a view of one channel is read in place); returns a dense
+        (H, W) map for run(..., m_map=...)."""
+        import torch
+        if not (isinstance(plane, torch.Tensor) and plane.is_cuda and plane.dtype == torch.float32
+                and plane.dim() == 2):
+            raise TypeError("plane must be a 2-D CUDA float32 tensor")
+        rp, _ = _pitches(plane)
+        H, W = plane.shape
+        out = out if out is not None else torch.empty((H, W), dtype=torch.float32, device=plane.device)
+        if tuple(out.shape) != (H, W) or not out.is_contiguous() or out.dtype != torch.float32:
+            raise ValueError("out must be a contiguous float32 (H, W) tensor")
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().fourier_llf_boost_map(self._ctx, plane.data_ptr(), W, H, rp, int(radius), float(m_max),
+                                           float(v_half), out.data_ptr(), sptr), self._ctx)
         return out
 
     def run_batch(self, jobs: Sequence[Job], stream=None) -> List["object"]:

@@ -14,21 +14,23 @@ from oracle import fourier_llf_ref as ref
 
 
 def _one(args):
-    kind, plane, levels, sigma, m, K, T, mmap = args
+    kind, plane, levels, sigma, m, K, T, mmap, smap = args
     if kind == "adaptive":
-        return ref.fourier_llf_adaptive(plane, levels, sigma, mmap, K, T=T)
+        return ref.fourier_llf_adaptive(plane, levels, sigma, mmap, K, T=T, sigma_map=smap, m=m)
     return ref.fourier_llf(plane, levels, sigma, m, K, T=T)
 
 
-def oracle_channels(img, levels, sigma, m, K, T=None, m_map=None, workers=None):
+def oracle_channels(img, levels, sigma, m, K, T=None, m_map=None, workers=None, sigma_map=None):
     """Per-channel oracle output of a (C, H, W) image as a float64 (C, H, W)
-    array; with m_map the pixel-by-pixel form (one map shared by the channels)."""
+    array; with m_map and/or sigma_map the pixel-by-pixel form (maps shared by
+    the channels)."""
     img = np.asarray(img, dtype=np.float64)
     if img.ndim == 2:
         img = img[None]
-    kind = "plain" if m_map is None else "adaptive"
+    kind = "plain" if m_map is None and sigma_map is None else "adaptive"
     mm = None if m_map is None else np.asarray(m_map, dtype=np.float64)
-    jobs = [(kind, img[c], levels, sigma, m, K, T, mm) for c in range(img.shape[0])]
+    sm = None if sigma_map is None else np.asarray(sigma_map, dtype=np.float64)
+    jobs = [(kind, img[c], levels, sigma, m, K, T, mm, sm) for c in range(img.shape[0])]
     n = workers or min(len(jobs), 16, os.cpu_count() or 1)
     if n <= 1 or len(jobs) == 1:
         return np.stack([_one(j) for j in jobs])

@@ -214,3 +214,39 @@ def test_footprint_does_not_depend_on_pitches(F):
     a = F.footprint([_job(F, channels=3)])
     b = F.footprint([_job(F, channels=3, pitches=(100, 10000, 128, 128 * 48))])
     assert a == b
+
+
+# --- pixel-by-pixel range scale (sigma_map) ---------------------------------------
+
+@pytest.mark.parametrize("lo,hi,K", [(0.05, 0.3, 8), (0.1, 0.2, 4), (0.08, 0.12, 16), (0.15, 0.15, 8)])
+def test_fit_range_matches_oracle(F, lo, hi, K):
+    T = F.fit_range(lo, hi, K)
+    Tr = ref.fit_period_range(lo, hi, K)
+    assert abs(T - Tr) / Tr < 1e-7
+    if lo == hi:
+        assert abs(T - F.fit(lo, K)[0]) <= 1e-12 * T
+
+
+def test_fit_range_rejects_bad_ranges(F):
+    with pytest.raises(F.FourierLLFError):
+        F.fit_range(0.2, 0.1, 8)
+    with pytest.raises(F.FourierLLFError):
+        F.fit_range(0.0, 0.1, 8)
+
+
+def test_validate_sigma_map(F):
+    ok = _job(F, sigma_map_ptr=0x700000000, sigma_max=0.3)
+    assert F.validate([ok]) == F.FLLF_OK
+    # sigma_max must bound the map from above (sigma_r is its smallest value)
+    assert F.validate([_job(F, sigma_map_ptr=0x700000000, sigma_max=0.1)]) == F.FLLF_EINVAL
+    assert "sigma_max" in F.last_error()
+    # the map must not overlap the output
+    assert F.validate([_job(F, sigma_map_ptr=0x100000000 + 64, sigma_max=0.3)]) == F.FLLF_EINVAL
+
+
+def test_footprint_of_maps(F):
+    # each map adds one float32 plane per level 1 .. top-1, shared by the channels
+    plain = F.footprint([_job(F, channels=3)])
+    one = F.footprint([_job(F, channels=3, m_map_ptr=0x700000000)])
+    two = F.footprint([_job(F, channels=3, m_map_ptr=0x700000000, sigma_map_ptr=0x800000000, sigma_max=0.3)])
+    assert one > plain and two - one == one - plain
