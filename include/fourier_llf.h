@@ -59,6 +59,17 @@ typedef enum {
 
 typedef struct fllf_ctx fllf_ctx; /* opaque, host-side state only */
 
+/* fllf_job.flags: run the fast LLF comparator (Sec. II-C) instead of Fourier LLF:
+ * the remap r(i, g) = i + m (i - g) exp(-(i - g)^2 / 2 sigma_r^2) is sampled at K
+ * intensities tau j, j = 0 .. K-1, tau = R / (K - 1) (K even, 2..32), the
+ * Laplacian pyramids of the K remapped images are built (K + 1 pyramids with
+ * G_l[I]), and at every level-l pixel p the output coefficient interpolates
+ * them linearly at g = G_l[I]_p (clamped to [0, R]); the top level is
+ * G_lmax[I].  Same kernels (REDUCE, EXPAND, collapse) with the sampled remaps in
+ * place of the Fourier pairs.  Single-job runs only (n = 1; not batched, not
+ * served, no maps, period_T = 0). */
+#define FLLF_FLAG_FAST_LLF 1
+
 /* One image to filter (Sec. II-A problem statement: image, levels, sigma_r, m, K).
  * Zero-initialise the struct: every field added after m_map means "dense" or
  * "absent" when 0. */
@@ -71,8 +82,8 @@ typedef struct {
   int32_t channels;  /* >= 1; each channel is filtered independently */
   int32_t levels;    /* |L| >= 1, counts the residual level;
                         at most fourier_llf_max_levels(height, width) and FLLF_MAX_LEVELS */
-  int32_t K;         /* number of Fourier terms, 1..FLLF_MAX_K */
-  int32_t flags;     /* must be 0 */
+  int32_t K;         /* number of Fourier terms, 1..FLLF_MAX_K (fast LLF: samples, see flags) */
+  int32_t flags;     /* 0, or FLLF_FLAG_FAST_LLF */
   double sigma_r;    /* range scale of the remap (Eq. (6)), > 0, same units as the pixels */
   double m;          /* detail boost of Eq. (6): > 0 enhance, < 0 smooth, 0 identity */
   double range_R;    /* intensity range R of Eq. (12) (1.0 for [0,1] images), > 0 */

@@ -340,11 +340,12 @@ def fourier_llf_adaptive(I: np.ndarray, levels: int, sigma_r: float, m_map: np.n
 # --------------------------------------------------------------------------- #
 # Brute force: the definition of LLF (Sec. II-C, Eq. (13))
 # --------------------------------------------------------------------------- #
-def naive_llf(I: np.ndarray, levels: int,
-              remap: Callable[[np.ndarray, float], np.ndarray]) -> np.ndarray:
-    """Naive LLF: for every level l < l_max and every level-l pixel p, remap the
-    whole input with g = G_l[I]_p, build its pyramid to level l+1 and keep
-    L_l[r(I, g)]_p (Eq. (13)); L_lmax[O] = G_lmax[I]; then collapse (Eq. (4)).
+def naive_llf_pyramid(I: np.ndarray, levels: int,
+                      remap: Callable[[np.ndarray, float], np.ndarray]) -> List[np.ndarray]:
+    """The output Laplacian pyramid of naive LLF (Eq. (13)): for every level
+    l < l_max and every level-l pixel p, remap the whole input with
+    g = G_l[I]_p, build its pyramid to level l+1 and keep L_l[r(I, g)]_p;
+    L_lmax[O] = G_lmax[I].  Level l < l_max does not depend on |L|.
 
     O(N^2) per level: tiny images only.
     """
@@ -361,7 +362,13 @@ def naive_llf(I: np.ndarray, levels: int,
                 out[y, x] = lap[y, x]
         LO.append(out)
     LO.append(G[levels - 1])
-    return collapse(LO)
+    return LO
+
+
+def naive_llf(I: np.ndarray, levels: int,
+              remap: Callable[[np.ndarray, float], np.ndarray]) -> np.ndarray:
+    """Naive LLF: the collapse (Eq. (4)) of naive_llf_pyramid."""
+    return collapse(naive_llf_pyramid(I, levels, remap))
 
 
 def naive_llf_adaptive(I: np.ndarray, levels: int, remap: Callable[..., np.ndarray],

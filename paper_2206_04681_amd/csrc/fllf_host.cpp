@@ -183,7 +183,8 @@ void fourier_terms(double s, int K, double T, double *omega, double *alpha_tilde
 void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p) {
   std::memset(p, 0, sizeof(*p));
   p->levels = job.levels;
-  p->K = job.K;
+  p->fast = (job.flags & FLLF_FLAG_FAST_LLF) != 0;
+  p->K = p->fast ? job.K / 2 : job.K;
   p->C = job.channels;
   p->dwp = storage == FLLF_STORE_F32 ? 2 : 1;
   p->in = job.in;
@@ -200,7 +201,7 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
     L.pitch = l == 0 ? (int)job_in_rp(job) : (int)align_up((size_t)w, 64);
     L.n = (size_t)w * h;
     const size_t g_plane = align_up((size_t)L.pitch * h * 4);
-    const size_t cs_plane = align_up((size_t)L.pitch * h * pair_bytes * job.K);
+    const size_t cs_plane = align_up((size_t)L.pitch * h * pair_bytes * p->K);
     L.g_cstride = g_plane / 4;
     L.cs_kstride = 1;
     L.cs_cstride = cs_plane / pair_bytes;
@@ -240,6 +241,18 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
   cp.dstride = p->out_cs * sizeof(float);
   cp.C = job.channels;
 
+  if (p->fast) {  // the sampled remap: no period, no alpha~
+    const int n = job.K;
+    p->coefs.m = (float)job.m;
+    p->coefs.K = p->K;
+    p->coefs.fast = 1;
+    p->coefs.tau = (float)(job.range_R / (n - 1));
+    p->coefs.inv_tau = (float)((n - 1) / job.range_R);
+    p->coefs.rc = (float)(1.0 / (2.0 * job.sigma_r * job.sigma_r));
+    p->coefs.nm1 = (float)(n - 1);
+    for (int k = 0; k < kMaxK; ++k) p->coefs.at[k] = p->coefs.wt[k] = 1.0f;
+    return;
+  }
   const double T = job.period_T > 0.0 ? job.period_T
                    : job.sigma_map  ? fit_period_range(job.sigma_r, job.sigma_max, job.K, job.range_R)
                                     : fit_period(job.sigma_r, job.K, job.range_R);
@@ -342,9 +355,18 @@ static fllf_status validate(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_sto
     if (j.levels < 1 || j.levels > maxL)
       return fail(ctx, FLLF_EINVAL, "job %d: levels=%d outside [1, %d] for %d x %d", i, j.levels, maxL,
                   j.width, j.height);
-    if (j.K < 1 || j.K > FLLF_MAX_K)
+    if (j.flags & ~FLLF_FLAG_FAST_LLF) return fail(ctx, FLLF_EINVAL, "job %d: unknown flags 0x%x", i, j.flags);
+    const bool fast = (j.flags & FLLF_FLAG_FAST_LLF) != 0;
+    if (fast) {
+      if (j.K < 2 || j.K > 32 || (j.K & 1))
+        return fail(ctx, FLLF_EINVAL, "job %d: fast LLF needs an even number of samples K in [2, 32] (K=%d)", i, j.K);
+      if (j.period_T != 0.0) return fail(ctx, FLLF_EINVAL, "job %d: fast LLF has no period (period_T must be 0)", i);
+      if (j.m_map || j.sigma_map) return fail(ctx, FLLF_EUNSUPPORTED, "job %d: fast LLF takes no per-pixel maps", i);
+      if (n > 1) return fail(ctx, FLLF_EUNSUPPORTED, "job %d: fast LLF runs as a single job", i);
+    } else if (j.K < 1 || j.K > FLLF_MAX_K) {
       return fail(ctx, FLLF_EINVAL, "job %d: K=%d outside [1, %d]", i, j.K, FLLF_MAX_K);
-    if (j.flags != 0) return fail(ctx, FLLF_EINVAL, "job %d: flags must be 0", i);
+    }
+    const int pairs = fast ? j.K / 2 : j.K;  // (cos, sin) pairs, or pairs of samples, per record
     if (!is_finite(j.sigma_r) || j.sigma_r <= 0.0)
       return fail(ctx, FLLF_EINVAL, "job %d: sigma_r must be finite and > 0", i);
     if (!is_finite(j.m)) return fail(ctx, FLLF_EINVAL, "job %d: m must be finite", i);
@@ -356,7 +378,7 @@ static fllf_status validate(fllf_ctx *ctx, const fllf_job *jobs, int n, fllf_sto
     // (the level-1 record plane) must stay below 4 GiB
     if (j.levels >= 2) {
       const uint64_t w1 = (uint64_t)(j.width + 1) / 2, h1 = (uint64_t)(j.height + 1) / 2;
-      const uint64_t rec_plane = fllf::align_up(w1, 64) * h1 * (uint64_t)j.K * 2u * storage_bytes(storage);
+      const uint64_t rec_plane = fllf::align_up(w1, 64) * h1 * (uint64_t)pairs * 2u * storage_bytes(storage);
       if (rec_plane >= ((uint64_t)1 << 32))
         return fail(ctx, FLLF_EINVAL, "job %d: %d x %d with K=%d needs a level-1 plane of %llu bytes (limit 4 GiB)",
                     i, j.width, j.height, j.K, (unsigned long long)rec_plane);
@@ -708,6 +730,7 @@ fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_
     return fail(ctx, FLLF_EINVAL, "reparam: input, size, channels, levels, K and R must match the resident job");
   if (a.m_map || b.m_map || a.sigma_map || b.sigma_map)
     return fail(ctx, FLLF_EUNSUPPORTED, "reparam: per-pixel maps are not supported");
+  if (a.flags || b.flags) return fail(ctx, FLLF_EUNSUPPORTED, "reparam: Fourier LLF jobs only");
   if (b.K != 4 && b.K != 8 && b.K != 16) return fail(ctx, FLLF_EUNSUPPORTED, "reparam: K must be 4, 8 or 16");
   const double T = a.period_T > 0.0 ? a.period_T : fllf::fit_period(a.sigma_r, a.K, a.range_R);
   if (b.period_T != 0.0 && b.period_T != T)

@@ -34,6 +34,11 @@ struct Coefs {
   int has_mmap;     // 1: per-pixel boost read from the level's m plane
   int has_smap;     // 1: per-pixel range scale read from the level's sigma plane
   float sref, inv_sref, qk;
+  // fast LLF (the comparator of Sec. II-C): n samples tau j, j = 0 .. n-1, of the
+  // remap r(i, g) = i + m (i - g) exp(-(i - g)^2 rc), rc = 1 / (2 sigma_r^2); the
+  // records hold the pyramids of r(I, tau j) as n / 2 pairs (at[] = 1)
+  int fast;
+  float tau, inv_tau, rc, nm1;  // tau = R / (n - 1); nm1 = n - 1
   float at[kMaxK];  // alpha~_1 .. alpha~_K
   float wt[kMaxK];  // re-parameterisation: new / resident alpha~_k (1 otherwise)
 };
@@ -66,7 +71,8 @@ struct CopyDesc {
 hipError_t copy_image(const CopyDesc &d, hipStream_t stream);
 
 struct JobPlan {
-  int levels, K, C;
+  int levels, K, C;  // K: pairs per record (Fourier terms; for fast LLF, samples / 2)
+  bool fast;         // fast LLF comparator
   int dwp;           // dwords per stored (C~, S~) pair: 2 (float32) or 1 (16-bit)
   Level lv[kMaxLevels];
   size_t bytes;      // workspace bytes of this job

@@ -310,6 +310,22 @@ struct TermScale {
   }
 };
 
+// Fast LLF (Sec. II-C): the remap sampled at g, and the interpolation weight of
+// sample j at t = g / tau (clamped to [0, n-1]): the hat max(0, 1 - |t - j|),
+// which is (1 - a) at j = floor(t) and a at j + 1, a = t - j.
+__device__ inline float remap_at(float v, float g, const Coefs &cf) {
+  const float d = v - g;
+  return fmaf(cf.m * d, expf(-d * d * cf.rc), v);
+}
+__device__ inline float hat(float t, float j) { return fmaxf(0.f, 1.f - fabsf(t - j)); }
+__device__ inline float sample_pos(float g, const Coefs &cf) { return fminf(fmaxf(g * cf.inv_tau, 0.f), cf.nm1); }
+// Level 0: the interpolation of r(v, tau j) over j at g = v itself.
+__device__ inline float fast_level0(float v, const Coefs &cf) {
+  const float t = sample_pos(v, cf);
+  const float j = fminf(floorf(t), cf.nm1 - 1.f), w = t - j;
+  return fmaf(w, remap_at(v, (j + 1.f) * cf.tau, cf), (1.f - w) * remap_at(v, j * cf.tau, cf));
+}
+
 // Unnormalised horizontal REDUCE at the lane's even fine column 2j from its
 // samples v0 (2j), v1 (2j+1) and its neighbours': taps [1 4 6 4 1].
 // Each lane shift feeds exactly one add (folded into a DPP add), and the result
@@ -472,9 +488,13 @@ struct NoRing {};
 // K loops of at most 16 dwords per record (float32 K <= 8, 16-bit K <= 16).
 constexpr bool fusable(int K, int dwp) { return (K == 4 || K == 8 || K == 16) && K * dwp <= 16; }
 
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE>
+// FAST: the fast LLF comparator (Sec. II-C): the records hold the pyramids of the
+// sampled remaps r(I, tau j) (level 0: formed in registers), and the level-l
+// half interpolates them at G_l[I] (separate form only, no maps).
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE, bool FAST = false>
 struct DownWave {
   static_assert(!(L0 && FUSE), "level 0 has no Laplacian to finish");
+  static_assert(!(FAST && (MAP || FUSE)), "fast LLF runs the separate passes without maps");
   using PS = PairStore<ST>;
   static constexpr int DW = PS::DW;
   static constexpr int NR = KM * DW;  // dwords of a full record
@@ -602,7 +622,16 @@ struct DownWave {
     float oq = 0.f;
     if (MAP) vstep<ROLE>(hred(d.m0, d.m1), PM0, PM1, om);
     if (MAP) vstep<ROLE>(hred(d.s0, d.s1), PQ0, PQ1, oq);
-    if (L0) {
+    if (L0 && FAST) {
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {  // pair k: samples 2k and 2k + 1
+          const float ga = (float)(2 * k) * a.cf.tau, gb = (float)(2 * k + 1) * a.cf.tau;
+          vstep<ROLE>(hred(remap_at(d.g0, ga, a.cf), remap_at(d.g1, ga, a.cf)), PC0[k], PC1[k], oc[k]);
+          vstep<ROLE>(hred(remap_at(d.g0, gb, a.cf), remap_at(d.g1, gb, a.cf)), PS0[k], PS1[k], os[k]);
+        }
+      }
+    } else if (L0) {
       float s, cc;
       sincos2pi(d.g0 * a.cf.inv_T, s, cc);
       Harmonics h0;
@@ -634,7 +663,26 @@ struct DownWave {
     // that only feed the running sums); wave-uniform
     float A0 = 0.f, A1 = 0.f, c0 = 0.f, s0 = 0.f, c1 = 0.f, s1 = 0.f;
     const float m0 = MAP ? d.m0 : a.cf.m, m1 = MAP ? d.m1 : a.cf.m;
-    if (!L0 && r >= 2 * i0 && r < 2 * i1 && r < a.g.Hf) {
+    if (FAST && !L0 && r >= 2 * i0 && r < 2 * i1 && r < a.g.Hf) {
+      // the level-l half of fast LLF: the sampled remaps' level l interpolated at g
+      const float t0 = sample_pos(d.g0, a.cf), t1 = sample_pos(d.g1, a.cf);
+      float acc0 = 0.f, acc1 = 0.f;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (EX || k < K) {
+          const float2 q0 = PS::cvt(&d.q[k * DW]), q1 = PS::cvt(&d.q[NR + k * DW]);
+          const float ja = (float)(2 * k), jb = (float)(2 * k + 1);
+          acc0 = fmaf(hat(t0, ja), q0.x, fmaf(hat(t0, jb), q0.y, acc0));
+          acc1 = fmaf(hat(t1, ja), q1.x, fmaf(hat(t1, jb), q1.y, acc1));
+        }
+      }
+      if (writer) {
+        const Plane ap(a.af + (size_t)c * a.af_cs);
+        const uint32_t so = (uint32_t)r * (uint32_t)a.g.pf * 4u;
+        if (two) ap.st2(make_float2(acc0, acc1), vx, so);
+        else ap.st1(acc0, vx, so);
+      }
+    } else if (!L0 && r >= 2 * i0 && r < 2 * i1 && r < a.g.Hf) {
       sincos2pi(d.g0 * a.cf.inv_T, s0, c0);
       Harmonics h0;
       h0.init(c0, s0);
@@ -833,9 +881,9 @@ struct DownWave {
   }
 };
 
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE>
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool FUSE, bool FAST = false>
 __global__ void __launch_bounds__(256, down_waves_per_simd(KM, MAP, FUSE)) down_kernel(DownArgs a) {
-  using W = DownWave<ST, KM, EX, L0, MAP, FUSE>;
+  using W = DownWave<ST, KM, EX, L0, MAP, FUSE, FAST>;
   constexpr int SLICE = W::SLICE;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * SLICE];
   int lane, strip, seg, c;
@@ -991,9 +1039,14 @@ collapse_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restric
 // and every term is reweighted by wt[k] (new / previous alpha~_k).
 // FOLD (level 0 only): the collapse of level 1 is done here, on the fly:
 // O_1 - G_1 = (L_1[O] - G_1) + EXPAND(O_2) at every level-1 sample the pass reads.
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false, bool FOLD = false>
+// FAST: the fast LLF comparator: O_l = A_l - sum_j w_j(G_l[I]) EXPAND(G_{l+1}[r(I, tau j)])
+// + EXPAND(O_{l+1}) (O_top = G_top[I], passed as oc with oc_minus_g); at level 0
+// A_0 is the interpolation of r(I_p, tau j) at I_p.
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false, bool FOLD = false,
+          bool FAST = false>
 struct UpWave {
   static_assert(!FOLD || (L0 && HASD && !RW), "the level-1 collapse folds into up(0) only");
+  static_assert(!FAST || (HASD && !MAP && !RW && !FOLD), "fast LLF: separate passes, O_{l+1} always given");
   using PS = PairStore<ST>;
   static constexpr int DW = PS::DW;
   static constexpr int NR = KM * DW;
@@ -1185,11 +1238,16 @@ struct UpWave {
       Harmonics hm[4];
       TermScale ts[4];
       float acc[4];
+      float tp[4];  // FAST: sample positions of G_l[I]
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        float s, cc;
-        sincos2pi(fa.g[p] * a.cf.inv_T, s, cc);
-        hm[p].init(cc, s);
+        if (FAST) {
+          tp[p] = sample_pos(fa.g[p], a.cf);
+        } else {
+          float s, cc;
+          sincos2pi(fa.g[p] * a.cf.inv_T, s, cc);
+          hm[p].init(cc, s);
+        }
         if (MAP) ts[p].init(fa.s[p], a.cf);
         acc[p] = 0.f;
       }
@@ -1202,13 +1260,15 @@ struct UpWave {
           expand4(Sm[k], S0[k], v.y, ES);
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
-            if (MAP) {
+            if (FAST) {
+              acc[p] = fmaf(hat(tp[p], (float)(2 * k)), EC[p], fmaf(hat(tp[p], (float)(2 * k + 1)), ES[p], acc[p]));
+            } else if (MAP) {
               acc[p] = fmaf(ts[p].e, fmaf(hm[p].s, EC[p], -hm[p].c * ES[p]), acc[p]);
               ts[p].next();
             } else {
               acc[p] = fmaf(hm[p].s, EC[p], fmaf(-hm[p].c, ES[p], acc[p]));
             }
-            hm[p].next();
+            if (!FAST) hm[p].next();
           }
           Cm[k] = C0[k];
           C0[k] = v.x;
@@ -1225,8 +1285,9 @@ struct UpWave {
       float o[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const float mp = MAP ? fa.m[p] : a.cf.m;
-        const float bp = L0 ? fa.g[p] : fa.b[p];
+        // fast LLF subtracts the interpolated EXPAND of the sampled remaps
+        const float mp = FAST ? -1.f : MAP ? fa.m[p] : a.cf.m;
+        const float bp = L0 ? (FAST ? fast_level0(fa.g[p], a.cf) : fa.g[p]) : fa.b[p];
         o[p] = fmaf(scl[p], fmaf(mp, acc[p], ED[p]), bp);
         // computed by every lane here: keeps the arithmetic next to its lane
         // shifts, which then fold into DPP adds (else it sinks into the
@@ -1257,9 +1318,10 @@ struct UpWave {
   }
 };
 
-template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false, bool FOLD = false>
+template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false, bool FOLD = false,
+          bool FAST = false>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs a) {
-  using W = UpWave<ST, KM, EX, L0, MAP, HASD, RW, FOLD>;
+  using W = UpWave<ST, KM, EX, L0, MAP, HASD, RW, FOLD, FAST>;
   __shared__ __attribute__((aligned(16))) uint32_t stage[4 * W::SLICE];
   int lane, strip, seg, c;
   if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
@@ -1373,7 +1435,7 @@ inline long geom_waves(const Geom &g) { return (long)g.nstrips * g.nsegs * g.C; 
 // result does not depend on the jobs batched with it.
 constexpr double kFuseMinSamples = 1 << 20;
 inline bool fused_level(const JobPlan &P, int l) {
-  return l >= 1 && fusable(P.K, P.dwp) && (double)P.lv[l].n * P.C >= kFuseMinSamples;
+  return l >= 1 && !P.fast && fusable(P.K, P.dwp) && (double)P.lv[l].n * P.C >= kFuseMinSamples;
 }
 
 // A fused level 1 below the top has its collapse folded into up(0), which then
@@ -1481,6 +1543,10 @@ inline UpArgs make_up_args(const JobPlan &P, int l, char *ws, int dwp, const Tun
     a.h2 = lv[2].h;
     a.p2 = lv[2].pitch;
   }
+  if (P.fast) {  // O_{l+1}, or G_top[I] (the residual level) at the top; G_{l+1} is not subtracted
+    a.oc = (const float *)(ws + (hasd ? lv[l + 1].off_o : lv[l + 1].off_g));
+    a.oc_minus_g = 1;
+  }
   a.g = pass_geom(P, l, false, tu, reparam);
   if (l == 0) {  // the caller's output and map rows
     a.g.po = P.out_pitch;
@@ -1505,7 +1571,8 @@ inline double up_bytes(const JobPlan &P, int l, int dwp, bool reparam = false) {
   if (!reparam && fused_level(P, l)) return C * (8.0 * lv[l].n + 4.0 * lv[l + 1].n);  // L_l, O_l; O_{l+1}
   const bool fold = l == 0 && hasd && !reparam && fused_level(P, 1);  // L_1[O] - G_1, and O_2
   const double fine = l == 0 ? 4.0 : 8.0;                               // I, or A_l and G_l
-  const double coarse = (fold ? 0.0 : 4.0) + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
+  const double coarse = P.fast ? pb + 4.0                               // pairs, O_{l+1} (G_top)
+                               : (fold ? 0.0 : 4.0) + pb + (hasd ? 4.0 : 0.0);  // G, pairs, O_{l+1}
   const double o2 = fold ? 4.0 * lv[2].n : 0.0;
   return C * ((fine + 4.0) * lv[l].n + coarse * lv[l + 1].n + o2) + mapb * lv[l].n;  // + O_l written
 }
@@ -1562,6 +1629,31 @@ hipError_t launch_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *
   return hipGetLastError();
 }
 
+// Fast LLF (single jobs): the separate down and up passes with the sampled-remap
+// basis; every up pass expands O_{l+1} (G_top[I] at the top).
+template <int ST, int KM, bool EX>
+hipError_t launch_fast_typed(const JobPlan &P, char *ws, hipStream_t st, LaunchHook *hook, const Tuning &tu) {
+  const int L = P.levels;
+  const int dwp = PairStore<ST>::DW;
+  for (int l = 0; l + 1 < L; ++l) {
+    const DownArgs a = make_down_args(P, l, ws, dwp, tu);
+    if (hook) hook->before(st);
+    if (l == 0) down_kernel<ST, KM, EX, true, false, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+    else down_kernel<ST, KM, EX, false, false, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+    if (hook) hook->after(st, kDownNames[l], down_bytes(P, l, dwp));
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const UpArgs a = make_up_args(P, l, ws, dwp, tu);
+    if (hook) hook->before(st);
+    if (l == 0)
+      up_kernel<ST, KM, EX, true, false, true, false, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+    else
+      up_kernel<ST, KM, EX, false, false, true, false, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
+    if (hook) hook->after(st, kUpNames[l], up_bytes(P, l, dwp));
+  }
+  return hipGetLastError();
+}
+
 // The K loop of a job: K == 4, 8, 16 run exact loops; other K run the next
 // larger loop with guards.
 inline void k_class(int K, int *km, bool *ex) {
@@ -1576,6 +1668,12 @@ hipError_t launch_storage(const JobPlan &P, char *ws, hipStream_t st, LaunchHook
   int km;
   bool ex;
   k_class(P.K, &km, &ex);
+  if (P.fast) {  // at most 16 pairs (32 samples)
+    if (ex) return km == 4 ? launch_fast_typed<ST, 4, true>(P, ws, st, h, tu)
+                           : km == 8 ? launch_fast_typed<ST, 8, true>(P, ws, st, h, tu)
+                                     : launch_fast_typed<ST, 16, true>(P, ws, st, h, tu);
+    return km == 8 ? launch_fast_typed<ST, 8, false>(P, ws, st, h, tu) : launch_fast_typed<ST, 16, false>(P, ws, st, h, tu);
+  }
 #define FLLF_LAUNCH(KM, EX) \
   return map ? launch_typed<ST, KM, EX, true>(P, ws, st, h, tu) : launch_typed<ST, KM, EX, false>(P, ws, st, h, tu)
   if (ex) {

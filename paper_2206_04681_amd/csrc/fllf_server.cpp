@@ -201,6 +201,7 @@ fllf_status fourier_llf_server_submit(fllf_server *s, const fllf_job *job, uint6
   const fllf_storage storage = fllf::ctx_storage(ctx);
   fllf_status st = fllf::validate_jobs(ctx, job, 1, storage);
   if (st != FLLF_OK) return st;
+  if (job->flags) return fllf::ctx_fail(ctx, FLLF_EUNSUPPORTED, "server_submit: Fourier LLF jobs only");
   auto hits = [&](const void *p, size_t bytes) { return fllf::spans_overlap(p, bytes, s->base, s->bytes); };
   if (hits(job->out, fllf::out_span(*job)) || hits(job->in, fllf::in_span(*job)) ||
       hits(job->m_map, fllf::map_span(*job)) || hits(job->sigma_map, fllf::map_span(*job)))

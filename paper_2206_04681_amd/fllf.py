@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfourier_llf.so")
 
 FLLF_OK, FLLF_EINVAL, FLLF_ENOMEM, FLLF_EDEVICE, FLLF_EUNSUPPORTED = 0, -1, -2, -3, -4
 FLLF_MAX_K = 32
+FLLF_FLAG_FAST_LLF = 1
 FLLF_MAX_LEVELS = 16
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -234,14 +235,14 @@ class Job:
 def make_job(in_ptr: int, out_ptr: int, width: int, height: int, channels: int, levels: int,
              sigma_r: float, m: float, K: int, R: float = 1.0, T: float = 0.0,
              m_map_ptr: int = 0, pitches: Sequence[int] = (0, 0, 0, 0), sigma_map_ptr: int = 0,
-             sigma_max: float = 0.0) -> FllfJob:
+             sigma_max: float = 0.0, flags: int = 0) -> FllfJob:
     """pitches = (row_pitch, plane_pitch, out_row_pitch, out_plane_pitch) in
     elements, 0 = dense."""
     j = FllfJob()
     j.in_ = in_ptr
     j.out = out_ptr
     j.width, j.height, j.channels = int(width), int(height), int(channels)
-    j.levels, j.K, j.flags = int(levels), int(K), 0
+    j.levels, j.K, j.flags = int(levels), int(K), int(flags)
     j.sigma_r, j.m, j.range_R, j.period_T = float(sigma_r), float(m), float(R), float(T)
     j.m_map = m_map_ptr or None
     j.row_pitch, j.plane_pitch, j.out_row_pitch, j.out_plane_pitch = (int(p) for p in pitches)
@@ -419,6 +420,14 @@ class FourierLLF:
         tensor when None; any view with contiguous rows otherwise); returns it."""
         fj, out = self._prepare(Job(x, levels, sigma_r, m, K, R, T, out, m_map, sigma_map, sigma_max))
         self.run_jobs([fj], stream=stream, keep=(out, m_map, sigma_map))
+        return out
+
+    def run_fast(self, x, levels: int, sigma_r: float, m: float, n: int, R: float = 1.0, out=None, stream=None):
+        """The fast LLF comparator (FLLF_FLAG_FAST_LLF): the detail remap sampled at
+        n equally spaced intensities in [0, R] (n even), n + 1 pyramids."""
+        fj, out = self._prepare(Job(x, levels, sigma_r, m, n, R, 0.0, out))
+        fj.flags = FLLF_FLAG_FAST_LLF
+        self.run_jobs([fj], stream=stream, keep=(out,))
         return out
 
     def run_static(self, x, levels: int, sigma_r: float, m: float, K: int, R: float = 1.0, T: float = 0.0,
