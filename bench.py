@@ -154,6 +154,25 @@ def kernel_profile(torch, ctx, fn, steps):
     return rows
 
 
+def minimal_bytes(w, storage):
+    """Bytes one filter of the image must move at least: the input read and the
+    output written once, and every stored level written once and read once --
+    G_l[I] and the 2K Fourier values at levels >= 1 (b_s bytes each), the output
+    Laplacian L_l[O] at levels 0 .. top-1 and the collapse O_l at levels
+    1 .. top-1; the level-0 Fourier values are formed in registers.  Per pixel
+    and channel about 24 + (4/3) K b_s bytes."""
+    bs = 4 if storage == "f32" else 2
+    n, (wd, ht) = [], (w.width, w.height)
+    for _ in range(w.levels):
+        n.append(wd * ht)
+        wd, ht = (wd + 1) // 2, (ht + 1) // 2
+    top = w.levels - 1
+    b = 8 * n[0] + sum(8 * n[l] for l in range(1, top + 1))            # I, O; G_l
+    b += sum(2 * 2 * w.K * bs * n[l] for l in range(1, top + 1))        # Fourier values
+    b += sum(8 * n[l] for l in range(0, top)) + sum(8 * n[l] for l in range(1, top))  # L_l[O], O_l
+    return w.channels * b
+
+
 def run_form(torch, fllf, storage, x, w, steps, warmup):
     ctx = fllf.FourierLLF(storage)
     out = torch.empty_like(x)
@@ -200,7 +219,8 @@ def run_batched(torch, fllf, storages, steps, warmup):
     log(f"generating the {len(ws)}-image uneven batch")
     xs = [torch.from_numpy(w.image()).cuda() for w in ws]
     mpix = sum(w.megapixels for w in ws)
-    res = {"images": len(ws), "mpix": round(mpix, 3),
+    cmpix = sum(w.megapixels * w.channels for w in ws)  # channel-pixels: RGB images count three times
+    res = {"images": len(ws), "mpix": round(mpix, 3), "channel_mpix": round(cmpix, 3),
            "gray": sum(1 for w in ws if w.channels == 1), "rgb": sum(1 for w in ws if w.channels == 3),
            "K": ws[0].K, "levels": sorted({w.levels for w in ws})}
     for storage in storages:
@@ -230,6 +250,7 @@ def run_batched(torch, fllf, storages, steps, warmup):
         log(f"batched {storage}: per-image {t_loop:.3f} ms, batched {t_batch:.3f} ms, "
             f"autotuned {t_tuned:.3f} ms, graph {t_graph:.3f} ms (tuning {chosen})")
         res[storage] = {"value": round(mpix / (best * 1e-3), 2), "unit": "MPix/s",
+                        "channel_mpix_per_s": round(cmpix / (best * 1e-3), 2),
                         "ms_per_batch": round(best, 4),
                         "ms_per_image_loop": round(t_loop, 4), "ms_batched": round(t_batch, 4),
                         "ms_autotuned": round(t_tuned, 4), "ms_graph": round(t_graph, 4),
@@ -402,7 +423,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving form")
     ap.add_argument("--no-reparam", action="store_true", help="skip the re-parameterisation timing")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="requests per second")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the request stream")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the request stream")
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="arena for the server (0: half of the free device memory)")
     ap.add_argument("--serve-small-budget-gb", type=float, default=8.0,
@@ -448,6 +469,9 @@ def main():
 
     main_key = args.forms.split(",")[0]  # f32 unless a run selects other forms
     main_form = forms[main_key]
+    # per channel-pixel, to set the batched form (half of its images gray) beside the RGB image
+    for k, f in forms.items():
+        f["channel_mpix_per_s"] = round(w.channels * w.height * w.width / 1e6 / (f["ms"] * 1e-3), 2)
     copy_gbs = copy_bandwidth(torch)
     ms = main_form["ms"]
     mpix = w.height * w.width / 1e6
@@ -475,11 +499,17 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom["name"]), "avg_launch_us": round(dom_avg_s * 1e6, 2),
                      "alg_bytes_per_launch": int(dom_bytes)},
+        "channel_mpix_per_s": main_form["channel_mpix_per_s"],
         "ms_p50": round(main_form["p50"], 5),
         "ms_p90": round(main_form["p90"], 5),
         "ms_graph_replay": round(main_form["ms_graph"], 5),
         "ms_cold_mall_p50": round(main_form["cold50"], 5),
         "ms_cold_mall_p90": round(main_form["cold90"], 5),
+        # the whole step against the 8 TB/s peak on the minimal bytes of a filter
+        # (each stored level written and read once; see minimal_bytes), and on
+        # the bytes this schedule moves by design (level-1 records read twice)
+        "step_min_bytes": minimal_bytes(w, main_key),
+        "step_frac_min_bytes": round(minimal_bytes(w, main_key) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "step_alg_gbs": round(main_form["alg_bytes_per_step"] / (ms * 1e-3) / 1e9, 1),
         "copy_gbs_measured": round(copy_gbs, 1),
         "kernels": {k: [dict(name=r["name"], launches=r["launches"] // args.steps,
@@ -491,7 +521,10 @@ def main():
             result[f"{k}_store"] = {"value": round(mpix / (f["ms"] * 1e-3), 2), "unit": "MPix/s",
                                     "ms_per_step": round(f["ms"], 5), "ms_graph_replay": round(f["ms_graph"], 5),
                                     "ms_cold_mall_p50": round(f["cold50"], 5),
-                                    "speedup_vs_f32": round(ms / f["ms"], 3)}
+                                    "speedup_vs_f32": round(ms / f["ms"], 3),
+                                    "channel_mpix_per_s": f["channel_mpix_per_s"],
+                                    "step_frac_min_bytes": round(minimal_bytes(w, k) / (f["ms"] * 1e-3) / 1e9
+                                                                 / HBM_PEAK_GBS, 4)}
     if not args.no_reparam:
         result["reparam"] = run_reparam(torch, fllf, x, w, args.steps, args.warmup, ms)
     if not args.no_batch:

@@ -215,6 +215,17 @@ fllf_status fourier_llf_get_tuning(const fllf_ctx *ctx, int32_t *params);
 fllf_status fourier_llf_autotune(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
                                  size_t ws_bytes, void *hip_stream, int reps, int32_t *chosen);
 
+/* Autotuner with a persistent cache: the launch shape of a job set depends only
+ * on the device, the storage and each job's size, channels, levels, K, flags
+ * and maps (not on sigma_r or m).  If the text file `cache_path` holds an entry
+ * for that key, its parameters are set in the context without timing anything;
+ * otherwise this runs fourier_llf_autotune and appends the result as one line
+ * "<key> <p0> .. <p4>" (a missing file is created; unreadable lines are
+ * skipped).  Otherwise as fourier_llf_autotune. */
+fllf_status fourier_llf_autotune_cached(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
+                                        size_t ws_bytes, void *hip_stream, int reps, const char *cache_path,
+                                        int32_t *chosen);
+
 /* ---- captured schedules (HIP graphs) ------------------------------------- */
 
 typedef struct fllf_graph fllf_graph; /* opaque */

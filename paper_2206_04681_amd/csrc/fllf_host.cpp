@@ -836,6 +836,76 @@ fllf_status fourier_llf_autotune(fllf_ctx *ctx, const fllf_job *jobs, int n, voi
   return FLLF_OK;
 }
 
+// Key of a job set's launch shape: FNV-1a over the device (architecture and
+// compute units), the storage and, per job, everything planning depends on.
+static uint64_t tuning_key(const fllf_ctx *ctx, const fllf_job *jobs, int n) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t len) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < len; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+    mix(prop.gcnArchName, std::strlen(prop.gcnArchName));
+    mix(&prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
+  }
+  const int st = (int)ctx->storage;
+  mix(&st, sizeof(st));
+  mix(&n, sizeof(n));
+  for (int i = 0; i < n; ++i) {
+    const fllf_job &j = jobs[i];
+    const int32_t v[9] = {j.width, j.height, j.channels, j.levels, j.K, j.flags, j.m_map ? 1 : 0,
+                          j.sigma_map ? 1 : 0, 0};
+    mix(v, sizeof(v));
+  }
+  return h;
+}
+
+fllf_status fourier_llf_autotune_cached(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
+                                        size_t ws_bytes, void *hip_stream, int reps, const char *cache_path,
+                                        int32_t *chosen) {
+  if (!ctx || !cache_path) return fail(ctx, FLLF_EINVAL, "autotune_cached: ctx and cache_path must be non-NULL");
+  std::vector<fllf::JobPlan> plans;
+  fllf_status st = prepare(ctx, "autotune_cached", jobs, n, workspace, ws_bytes, &plans);
+  if (st != FLLF_OK) return st;
+  char key[32];
+  std::snprintf(key, sizeof(key), "%016llx", (unsigned long long)tuning_key(ctx, jobs, n));
+  if (FILE *f = std::fopen(cache_path, "r")) {
+    char line[256];
+    bool found = false;
+    int32_t p[fllf::kTuneParams] = {0};
+    while (!found && std::fgets(line, sizeof(line), f)) {
+      char k[32];
+      int v[fllf::kTuneParams];
+      if (std::sscanf(line, "%31s %d %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3], &v[4]) == 1 + fllf::kTuneParams &&
+          std::strcmp(k, key) == 0) {
+        for (int i = 0; i < fllf::kTuneParams; ++i) p[i] = v[i];
+        found = true;
+      }
+    }
+    std::fclose(f);
+    if (found) {
+      st = fourier_llf_set_tuning(ctx, p);  // checks the values read
+      if (st == FLLF_OK && chosen)
+        for (int i = 0; i < fllf::kTuneParams; ++i) chosen[i] = ctx->tune.p[i];
+      return st;
+    }
+  }
+  int32_t best[fllf::kTuneParams];
+  st = fourier_llf_autotune(ctx, jobs, n, workspace, ws_bytes, hip_stream, reps, best);
+  if (st != FLLF_OK) return st;
+  if (chosen)
+    for (int i = 0; i < fllf::kTuneParams; ++i) chosen[i] = best[i];
+  FILE *f = std::fopen(cache_path, "a");
+  if (!f) return fail(ctx, FLLF_EINVAL, "autotune_cached: cannot append to %s", cache_path);
+  char line[128];
+  const int len = std::snprintf(line, sizeof(line), "%s %d %d %d %d %d\n", key, best[0], best[1], best[2], best[3],
+                                best[4]);
+  const bool ok = std::fwrite(line, 1, (size_t)len, f) == (size_t)len;
+  if (std::fclose(f) != 0 || !ok) return fail(ctx, FLLF_EINVAL, "autotune_cached: cannot write %s", cache_path);
+  return FLLF_OK;
+}
+
 fllf_status fourier_llf_graph_create(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
                                      size_t ws_bytes, fllf_graph **out) {
   if (!out) return fail(ctx, FLLF_EINVAL, "graph_create: out is NULL");

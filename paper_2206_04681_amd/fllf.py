@@ -33,7 +33,7 @@ EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run
             "fourier_llf_server_create", "fourier_llf_server_submit", "fourier_llf_server_step",
             "fourier_llf_server_poll", "fourier_llf_server_stats", "fourier_llf_server_destroy",
             "fourier_llf_reparam", "fourier_llf_run_static", "fourier_llf_fit_range",
-            "fourier_llf_boost_map")
+            "fourier_llf_boost_map", "fourier_llf_autotune_cached")
 
 # Launch-shape parameters (FLLF_TUNE_*): target waves of the REDUCE pass from
 # level 0 and from levels >= 1, of the up passes that evaluate the product-sum
@@ -132,6 +132,8 @@ def lib() -> ctypes.CDLL:
         L.fourier_llf_get_tuning.restype = i32
         L.fourier_llf_autotune.argtypes = [vp, jp, i32, vp, sz, vp, i32, ip]
         L.fourier_llf_autotune.restype = i32
+        L.fourier_llf_autotune_cached.argtypes = [vp, jp, i32, vp, sz, vp, i32, ctypes.c_char_p, ip]
+        L.fourier_llf_autotune_cached.restype = i32
         L.fourier_llf_graph_create.argtypes = [vp, jp, i32, vp, sz, ctypes.POINTER(vp)]
         L.fourier_llf_graph_create.restype = i32
         L.fourier_llf_graph_launch.argtypes = [vp, vp]
@@ -388,8 +390,11 @@ class FourierLLF:
         _check(lib().fourier_llf_get_tuning(self._ctx, arr), self._ctx)
         return list(arr)
 
-    def autotune(self, fjobs: Sequence[FllfJob], workspace=None, stream=None, reps: int = 3) -> List[int]:
-        """Time candidate launch shapes on these jobs and keep the fastest (synchronous)."""
+    def autotune(self, fjobs: Sequence[FllfJob], workspace=None, stream=None, reps: int = 3,
+                 cache: Optional[str] = None) -> List[int]:
+        """Time candidate launch shapes on these jobs and keep the fastest
+        (synchronous).  With `cache` (a file path) a stored result for the same
+        device, storage and job shapes is reused, and a new one is appended."""
         import torch
         arr = _job_array(fjobs)
         ws = workspace if workspace is not None else self.workspace(self.workspace_size(fjobs))
@@ -397,8 +402,12 @@ class FourierLLF:
             stream = torch.cuda.current_stream(self.device)
         sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         out = (ctypes.c_int32 * len(TUNE_NAMES))()
-        _check(lib().fourier_llf_autotune(self._ctx, arr, len(fjobs), ws.data_ptr(), ws.numel(), sptr,
-                                          int(reps), out), self._ctx)
+        if cache is None:
+            _check(lib().fourier_llf_autotune(self._ctx, arr, len(fjobs), ws.data_ptr(), ws.numel(), sptr,
+                                              int(reps), out), self._ctx)
+        else:
+            _check(lib().fourier_llf_autotune_cached(self._ctx, arr, len(fjobs), ws.data_ptr(), ws.numel(), sptr,
+                                                     int(reps), os.fsencode(cache), out), self._ctx)
         return list(out)
 
     def graph(self, fjobs: Sequence[FllfJob], workspace=None) -> "Graph":

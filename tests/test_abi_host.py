@@ -250,3 +250,26 @@ def test_footprint_of_maps(F):
     one = F.footprint([_job(F, channels=3, m_map_ptr=0x700000000)])
     two = F.footprint([_job(F, channels=3, m_map_ptr=0x700000000, sigma_map_ptr=0x800000000, sigma_max=0.3)])
     assert one > plain and two - one == one - plain
+
+
+# --- the fast LLF comparator (FLLF_FLAG_FAST_LLF) -----------------------------------
+
+def test_validate_fast_llf_jobs(F):
+    fast = dict(flags=F.FLLF_FLAG_FAST_LLF)
+    assert F.validate([_job(F, K=8, **fast)]) == F.FLLF_OK
+    assert F.validate([_job(F, K=32, **fast)]) == F.FLLF_OK
+    for K in (1, 7, 34):  # an even number of samples in [2, 32]
+        assert F.validate([_job(F, K=K, **fast)]) == F.FLLF_EINVAL
+    assert F.validate([_job(F, K=8, T=2.0, **fast)]) == F.FLLF_EINVAL  # no period
+    assert F.validate([_job(F, K=8, m_map_ptr=0x700000000, **fast)]) == F.FLLF_EUNSUPPORTED
+    other = dict(in_ptr=0x200000000, out_ptr=0x300000000)
+    assert F.validate([_job(F, K=8, **fast), _job(F, **other)]) == F.FLLF_EUNSUPPORTED  # single jobs only
+    assert F.validate([_job(F, flags=2)]) == F.FLLF_EINVAL
+    assert "flags" in F.last_error()
+
+
+def test_fast_llf_footprint_is_that_of_half_as_many_terms(F):
+    # n samples are stored as n / 2 pairs: the footprint of a Fourier job with K = n / 2
+    a = F.footprint([_job(F, K=12, flags=F.FLLF_FLAG_FAST_LLF)])
+    b = F.footprint([_job(F, K=6)])
+    assert a == b

@@ -166,6 +166,29 @@ def test_autotune_keeps_results(torch_dev):
         assert float((a - b).abs().max()) <= 1e-6
 
 
+def test_autotune_cache_round_trip(torch_dev, tmp_path):
+    torch = torch_dev
+    ctx = _ctx()
+    jobs, fjobs, outs = _mixed_jobs(torch, ctx, seed=90)
+    path = str(tmp_path / "tuning.txt")
+    first = ctx.autotune(fjobs, reps=1, cache=path)  # times, then appends one line
+    assert first == ctx.get_tuning()
+    assert len(open(path).read().strip().splitlines()) == 1
+    ctx.set_tuning(None)
+    assert ctx.autotune(fjobs, reps=1, cache=path) == first  # read back, nothing appended
+    assert ctx.get_tuning() == first
+    assert len(open(path).read().strip().splitlines()) == 1
+    # an entry written by hand is honoured; lines that are not entries are skipped
+    key = open(path).read().split()[0]
+    with open(path, "w") as f:
+        f.write("# launch shapes\nnot an entry\n" + f"{key} 1024 2048 3072 6144 2\n")
+    assert ctx.autotune(fjobs, reps=1, cache=path) == [1024, 2048, 3072, 6144, 2]
+    # another job set has another key: timed and appended
+    other = ctx.autotune(fjobs[:3], reps=1, cache=path)
+    assert len(open(path).read().strip().splitlines()) == 4 and other == ctx.get_tuning()
+    ctx.set_tuning(None)
+
+
 def test_uneven_batch_of_64_full_size(torch_dev):
     """The 64-image uneven batch at full size: batched == single-job runs for every
     image; the two smallest images, and every channel of the largest RGB image
