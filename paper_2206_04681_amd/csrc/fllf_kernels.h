@@ -1229,9 +1229,10 @@ struct UpWave {
     }
     const Plane op(outp);
     for (int i = i0; i < i1; ++i) {
-      load_c<BORDER>(rn, i + 2);
+      const bool more = i + 1 < i1;  // wave-uniform: the next rows are needed
+      if (more) load_c<BORDER>(rn, i + 2);
       ready<BORDER>(rp);
-      load_f<BORDER>(fb, i + 1 < i1 ? i + 1 : i);
+      if (more) load_f<BORDER>(fb, i + 1);
       const float Dp = HASD ? dval(rp) : 0.f;
       float ED[4] = {0.f, 0.f, 0.f, 0.f};
       if (HASD) expand4(Dm, D0, Dp, ED);
