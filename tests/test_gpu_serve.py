@@ -162,3 +162,46 @@ def test_images_inside_the_arena_are_refused(torch_dev):
         assert e.value.status == FLLF_EINVAL
     finally:
         srv.close()
+
+
+def test_maps_and_views_in_a_served_mix(torch_dev):
+    """Jobs with per-pixel boost and range-scale maps and strided input views,
+    served together with plain jobs: each equals the same job run alone; fast
+    LLF jobs are refused (single runs only)."""
+    torch = torch_dev
+    from paper_2206_04681_amd.fllf import (FourierLLF, FourierLLFError, Job, Server, FLLF_EUNSUPPORTED,
+                                           FLLF_FLAG_FAST_LLF)
+    llf = FourierLLF("f32")
+    srv = Server(llf, 1 << 30, max_active=16)
+    big = torch.from_numpy(synth_image(700, 900, 3, seed=41)).cuda()
+    yy, xx = np.mgrid[0:300, 0:400]
+    smap = torch.from_numpy((0.08 + 0.2 * xx / 399).astype(np.float32)).cuda()
+    mmap = torch.from_numpy((1.0 + 2.0 * yy / 299).astype(np.float32)).cuda()
+    jobs = [Job(big[:, 100:400, 200:600], 7, 0.08, 2.0, 8, sigma_map=smap, sigma_max=0.28),
+            Job(big[1, 50:350, 0:400], 6, 0.2, 0.0, 4, m_map=mmap),
+            Job(big[:, 0:300, 500:900], 6, 0.08, 0.0, 16, m_map=mmap, sigma_map=smap, sigma_max=0.28),
+            Job(big, 8, 0.1, 3.0, 8),
+            Job(big[2], 7, 0.15, 2.0, 5)]
+    try:
+        outs = [srv.submit(j, tag=i) for i, j in enumerate(jobs)]
+        done = set()
+        for _ in range(10000):
+            srv.step()
+            done.update(srv.poll())
+            if len(done) == len(jobs):
+                break
+        assert len(done) == len(jobs)
+        torch.cuda.synchronize()
+        for j, o in zip(jobs, outs):
+            alone = llf.run(j.x, j.levels, j.sigma_r, j.m, j.K, m_map=j.m_map, sigma_map=j.sigma_map,
+                            sigma_max=j.sigma_max)
+            torch.cuda.synchronize()
+            assert torch.equal(alone, o)
+        fj, _ = llf._prepare(Job(big[0], 5, 0.2, 2.0, 8))
+        fj.flags = FLLF_FLAG_FAST_LLF
+        from paper_2206_04681_amd.fllf import lib
+        import ctypes
+        st = lib().fourier_llf_server_submit(srv._s, ctypes.byref(fj), 99, None)
+        assert st == FLLF_EUNSUPPORTED
+    finally:
+        srv.close()
