@@ -120,3 +120,22 @@ def test_strided_batch_equals_single_runs(torch_dev):
     torch.cuda.synchronize()
     for v, p, o in zip(views, params, outs):
         assert torch.equal(o, _dense(torch, v, levels=p[0], sigma_r=p[1], m=p[2], K=p[3]))
+
+
+def test_strided_views_at_large_offsets(torch_dev):
+    """Rows 2^19 elements (2 MiB) apart: the last row of a 1100-row view starts
+    2.3 GB after the first, exercising the 32-bit plane offsets near their range
+    (a plane may span up to 2^30 elements).  Equal to the dense run bit for bit."""
+    torch = torch_dev
+    pitch, h, w = 1 << 19, 1100, 70
+    src = torch.zeros((h, pitch), device="cuda")
+    img = torch.from_numpy(synth_image(h, w, 1, seed=61)[0]).cuda()
+    src[:, 3:3 + w] = img
+    dst = torch.full((h, pitch), -9.0, device="cuda")
+    view_in, view_out = src[:, 3:3 + w], dst[:, 5:5 + w]
+    got = llf().run(view_in, 6, 0.2, 2.0, 8, out=view_out)
+    torch.cuda.synchronize()
+    want = _dense(torch, img, levels=6, sigma_r=0.2, m=2.0, K=8)
+    assert torch.equal(got, want)
+    assert float(dst[:, :5].max()) == -9.0 and float(dst[:, 5 + w:5 + w + 64].max()) == -9.0
+    del src, dst
