@@ -262,6 +262,10 @@ def _pitches(t) -> Tuple[int, int]:
         raise ValueError("image rows must be contiguous (last stride 1)")
     row = t.stride(-2) if t.shape[-2] > 1 else t.shape[-1]
     plane = t.stride(0) if t.dim() == 3 and t.shape[0] > 1 else 0
+    # a pitch of 0 means "dense" to the library: an expanded view (stride 0) must
+    # be materialised by the caller
+    if (t.shape[-2] > 1 and row == 0) or (t.dim() == 3 and t.shape[0] > 1 and plane == 0):
+        raise ValueError("image has a zero stride (an expanded view); pass a tensor with its own rows and planes")
     return int(row), int(plane)
 
 

@@ -273,3 +273,19 @@ def test_fast_llf_footprint_is_that_of_half_as_many_terms(F):
     a = F.footprint([_job(F, K=12, flags=F.FLLF_FLAG_FAST_LLF)])
     b = F.footprint([_job(F, K=6)])
     assert a == b
+
+
+def test_binding_pitches_of_views(F):
+    torch = pytest.importorskip("torch")
+    x = torch.zeros(3, 100, 90)
+    assert F._pitches(x) == (90, 9000)
+    assert F._pitches(x[:, 10:60, 5:80]) == (90, 9000)
+    assert F._pitches(x[1, 10:60, 5:80]) == (90, 0)
+    assert F._pitches(x.permute(1, 0, 2)[:, :3, :].permute(1, 0, 2)) == (90, 9000)
+    assert F._pitches(torch.zeros(100, 3, 90).permute(1, 0, 2)) == (270, 90)   # row-interleaved channels
+    with pytest.raises(ValueError):
+        F._pitches(x[:, :, ::2])                                     # rows not contiguous
+    with pytest.raises(ValueError):
+        F._pitches(torch.zeros(100, 90).expand(3, 100, 90))           # channels share their memory
+    with pytest.raises(ValueError):
+        F._pitches(torch.zeros(1, 90).expand(100, 90))                # rows share their memory
