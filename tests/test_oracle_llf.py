@@ -112,3 +112,17 @@ def test_adaptive_equals_bruteforce_with_per_pixel_remap():
     got = ref.fourier_llf_adaptive(I, 3, sigma, mmap, K, T=T)
     want = ref.naive_llf_adaptive(I, 3, lambda X, g, m: ref.remap_fourier(X, g, sigma, m, K, T), mmap)
     assert ref.max_abs(got, want) < 1e-12
+
+
+def test_naive_output_pyramid_levels_do_not_depend_on_the_level_count():
+    """Eq. (13): the level-l coefficient of naive LLF uses the pyramid of the
+    remapped image up to level l+1 only, so the output Laplacian levels below the
+    top are the same for every |L| (the accuracy experiment reuses them); the
+    collapse of the pyramid is naive_llf."""
+    I = np.random.default_rng(5).random((18, 22))
+    remap = lambda i, g: ref.remap_exact(i, g, 0.15, 2.0)
+    p4 = ref.naive_llf_pyramid(I, 4, remap)
+    p2 = ref.naive_llf_pyramid(I, 2, remap)
+    assert ref.max_abs(p4[0], p2[0]) == 0.0
+    assert ref.max_abs(p2[1], ref.gaussian_pyramid(I, 2)[1]) == 0.0
+    assert ref.max_abs(ref.collapse(p4), ref.naive_llf(I, 4, remap)) == 0.0
