@@ -116,15 +116,20 @@ typedef struct {
 } fllf_job;
 
 /* Create a context bound to HIP device `device` that stores the Fourier
- * pyramids as `storage`.  Fails with FLLF_EDEVICE when the device is absent. */
+ * pyramids (the 2K Gaussian Fourier pyramids of Eq. (14)) as `storage`.
+ * Fails with FLLF_EDEVICE when the device is absent. */
 fllf_status fourier_llf_create(fllf_ctx **out, int device, fllf_storage storage);
 
-/* Bytes of device workspace fourier_llf_run needs for these n jobs (n >= 1).
- * Equals the resident footprint of the jobs beyond their in/out images. */
+/* Bytes of device workspace fourier_llf_run needs for these n jobs (n >= 1):
+ * levels 1.. of the 2K+1 pyramids of Eq. (14) (Sec. III-A counts them) and the
+ * output Laplacian levels.  Equals the resident footprint of the jobs beyond
+ * their in/out images. */
 fllf_status fourier_llf_workspace_size(const fllf_ctx *ctx, const fllf_job *jobs, int n,
                                        size_t *bytes);
 
-/* Filter n jobs (n >= 1, sizes/K/sigma_r may differ) on `hip_stream` (a
+/* Filter n jobs -- the fit of Eq. (9)-(12), the pyramids of Eq. (1) and
+ * Eq. (14), the product-sum of Eq. (14) and the collapse of Eq. (4), per the
+ * problem statement of Sec. II-A -- (n >= 1, sizes/K/sigma_r may differ) on `hip_stream` (a
  * hipStream_t; NULL = the legacy default stream).  `workspace` is a device buffer
  * of at least the size returned by fourier_llf_workspace_size, 256-byte aligned,
  * owned by the caller and not used by anything else until the stream syncs.
@@ -143,7 +148,8 @@ fllf_status fourier_llf_run(fllf_ctx *ctx, const fllf_job *jobs, int n, void *wo
 /* Bytes of the library's own static workspace (256 MiB per device). */
 #define FLLF_STATIC_WORKSPACE_BYTES ((size_t)256 << 20)
 
-/* For callers that cannot allocate device memory (code under HIP stream
+/* (For callers that cannot allocate: the filter of fourier_llf_run.)
+ * For callers that cannot allocate device memory (code under HIP stream
  * capture, tight serving loops, harnesses that forbid hipMalloc): filters one
  * job exactly as fourier_llf_run(ctx, job, 1, ...) does (same kernels, same
  * result bit for bit) with the workspace taken from an array of
@@ -200,13 +206,15 @@ enum {
   FLLF_TUNE_PARAMS = 5
 };
 
-/* Set the context's parameters; params[i] <= 0 for i < FLLF_TUNE_GRID_CAP, or
+/* Launch shape only (no passage of the paper: results do not depend on it).
+ * Set the context's parameters; params[i] <= 0 for i < FLLF_TUNE_GRID_CAP, or
  * params == NULL, restores the built-in value.  Results do not depend on them. */
 fllf_status fourier_llf_set_tuning(fllf_ctx *ctx, const int32_t *params);
 /* Read the context's parameters into params[0 .. FLLF_TUNE_PARAMS-1]. */
 fllf_status fourier_llf_get_tuning(const fllf_ctx *ctx, int32_t *params);
 
-/* Autotuner: times fourier_llf_run of these jobs (same arguments as run) for
+/* (Launch shape only; no passage of the paper.)
+ * Autotuner: times fourier_llf_run of these jobs (same arguments as run) for
  * candidate values of each parameter in turn (coordinate descent; each
  * candidate 1 warm-up and `reps` timed runs, reps >= 1), keeps the fastest in
  * the context and writes them to chosen[0 .. FLLF_TUNE_PARAMS-1] (may be NULL).
@@ -230,7 +238,8 @@ fllf_status fourier_llf_autotune_cached(fllf_ctx *ctx, const fllf_job *jobs, int
 
 typedef struct fllf_graph fllf_graph; /* opaque */
 
-/* Capture the launches fourier_llf_run would make for these jobs into an
+/* (Scheduling of the filter of fourier_llf_run; no passage of the paper.)
+ * Capture the launches fourier_llf_run would make for these jobs into an
  * instantiated HIP graph.  The batch table is written to the workspace now
  * (synchronously); the graph binds the jobs' in/out/m_map pointers and the
  * workspace, which must stay valid and must not be used for anything else
@@ -242,16 +251,19 @@ fllf_status fourier_llf_graph_launch(fllf_graph *graph, void *hip_stream);
 /* Release the graph.  NULL-safe.  The caller must have synchronised its streams. */
 void fourier_llf_graph_destroy(fllf_graph *graph);
 
-/* Release the context.  NULL-safe.  The caller must have synchronised its streams. */
+/* Release the context.  NULL-safe.  The caller must have synchronised its streams.
+ * (Resource management; no passage of the paper.) */
 void fourier_llf_destroy(fllf_ctx *ctx);
 
-/* Human-readable reason for the last non-OK status returned on this thread
+/* (Error reporting; no passage of the paper.)
+ * Human-readable reason for the last non-OK status returned on this thread
  * (ctx may be NULL).  The string stays valid until the next call on this thread. */
 const char *fourier_llf_last_error(const fllf_ctx *ctx);
 
 /* ---- serving: continuous batching over a device arena --------------------- */
 
-/* A server runs many independent jobs that arrive over time.  Each job is the
+/* (Scheduling of the filter of fourier_llf_run; no passage of the paper.)
+ * A server runs many independent jobs that arrive over time.  Each job is the
  * same filter as fourier_llf_run (same result bit for bit); what differs is
  * the schedule.  Every fourier_llf_server_step
  *   1. admits queued jobs in arrival order while their workspace fits in the
@@ -331,7 +343,8 @@ fllf_status fourier_llf_boost_map(fllf_ctx *ctx, const float *in, int32_t width,
 
 /* ---- kernel timing (benchmarks) ------------------------------------------ */
 
-/* Aggregated device time of one kernel class over the launches recorded since
+/* (Measurement; no passage of the paper.)
+ * Aggregated device time of one kernel class over the launches recorded since
  * timing was enabled (or last read). */
 typedef struct {
   char name[32];      /* kernel class: "down_l<l>" (REDUCE from level l), "up_l<l>"
@@ -371,15 +384,18 @@ fllf_status fourier_llf_fit(double sigma_r, int K, double range_R, double T_in, 
  * is fourier_llf_fit's T.  The period a job with a sigma_map uses. */
 fllf_status fourier_llf_fit_range(double sigma_lo, double sigma_hi, int K, double range_R, double *T_out);
 
-/* Largest valid level count for an image: 1 + floor(log2(min(height, width))),
+/* The levels |L| of Sec. II-A, counting the residual level.
+ * Largest valid level count for an image: 1 + floor(log2(min(height, width))),
  * capped at FLLF_MAX_LEVELS; 0 for non-positive sizes. */
 int fourier_llf_max_levels(int height, int width);
 
-/* The parameter checks of fourier_llf_run without any device work
+/* The problem statement of Sec. II-A as fourier_llf_run checks it:
+ * the parameter checks of fourier_llf_run without any device work
  * (pointers are checked for NULL only). */
 fllf_status fourier_llf_validate(const fllf_job *jobs, int n, fllf_storage storage);
 
-/* Workspace bytes for these jobs with pyramid storage `storage`, without a
+/* The pyramids of Eq. (14), as fourier_llf_workspace_size counts them.
+ * Workspace bytes for these jobs with pyramid storage `storage`, without a
  * context or device (the same number fourier_llf_workspace_size returns).
  * Used for admission by device-memory footprint. */
 fllf_status fourier_llf_footprint(const fllf_job *jobs, int n, fllf_storage storage, size_t *bytes);
