@@ -196,19 +196,26 @@ fllf_status fourier_llf_reparam(fllf_ctx *ctx, const fllf_job *prev, const fllf_
  *     >= 1;
  *   FLLF_TUNE_GRID_CAP: 0 = a batched launch has one wave per work item; c > 0
  *     = at most c times the blocks resident on the device at once, each wave
- *     looping over work items (persistent launch). */
+ *     looping over work items (persistent launch);
+ *   FLLF_TUNE_NT_STORES: the pass kinds whose stores are non-temporal (not kept
+ *     in the caches for reuse), a bit set: 1 = REDUCE from level 0, 2 = REDUCE
+ *     from the levels >= 1 that take the fused form, 4 = the other REDUCE passes
+ *     from levels >= 1, 8 = the up pass to level 0, 16 = the up passes and
+ *     collapses to levels >= 1 (0..31). */
 enum {
   FLLF_TUNE_DOWN0 = 0,
   FLLF_TUNE_DOWN = 1,
   FLLF_TUNE_UP0 = 2,
   FLLF_TUNE_UP = 3,
   FLLF_TUNE_GRID_CAP = 4,
-  FLLF_TUNE_PARAMS = 5
+  FLLF_TUNE_NT_STORES = 5,
+  FLLF_TUNE_PARAMS = 6
 };
 
 /* Launch shape only (no passage of the paper: results do not depend on it).
- * Set the context's parameters; params[i] <= 0 for i < FLLF_TUNE_GRID_CAP, or
- * params == NULL, restores the built-in value.  Results do not depend on them. */
+ * Set the context's parameters; params[i] <= 0 for i < FLLF_TUNE_GRID_CAP,
+ * params[FLLF_TUNE_NT_STORES] < 0, or params == NULL, restores the built-in
+ * value.  Results do not depend on them. */
 fllf_status fourier_llf_set_tuning(fllf_ctx *ctx, const int32_t *params);
 /* Read the context's parameters into params[0 .. FLLF_TUNE_PARAMS-1]. */
 fllf_status fourier_llf_get_tuning(const fllf_ctx *ctx, int32_t *params);
@@ -228,7 +235,7 @@ fllf_status fourier_llf_autotune(fllf_ctx *ctx, const fllf_job *jobs, int n, voi
  * and maps (not on sigma_r or m).  If the text file `cache_path` holds an entry
  * for that key, its parameters are set in the context without timing anything;
  * otherwise this runs fourier_llf_autotune and appends the result as one line
- * "<key> <p0> .. <p4>" (a missing file is created; unreadable lines are
+ * "<key> <p0> .. <p5>" (a missing file is created; unreadable lines are
  * skipped).  Otherwise as fourier_llf_autotune. */
 fllf_status fourier_llf_autotune_cached(fllf_ctx *ctx, const fllf_job *jobs, int n, void *workspace,
                                         size_t ws_bytes, void *hip_stream, int reps, const char *cache_path,

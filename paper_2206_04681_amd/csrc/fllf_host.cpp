@@ -766,6 +766,10 @@ fllf_status fourier_llf_set_tuning(fllf_ctx *ctx, const int32_t *params) {
     if (params[fllf::kTuneGridCap] < 0 || params[fllf::kTuneGridCap] > 1024)
       return fail(ctx, FLLF_EINVAL, "set_tuning: grid cap %d outside [0, 1024]", params[fllf::kTuneGridCap]);
     t.p[fllf::kTuneGridCap] = params[fllf::kTuneGridCap];
+    if (params[fllf::kTuneNtStores] > fllf::kNtAll)
+      return fail(ctx, FLLF_EINVAL, "set_tuning: nt_stores %d outside [0, %d]", params[fllf::kTuneNtStores],
+                  fllf::kNtAll);
+    if (params[fllf::kTuneNtStores] >= 0) t.p[fllf::kTuneNtStores] = params[fllf::kTuneNtStores];
   }
   ctx->tune = t;
   return FLLF_OK;
@@ -808,12 +812,16 @@ fllf_status fourier_llf_autotune(fllf_ctx *ctx, const fllf_job *jobs, int n, voi
   };
   static const int kWaves[] = {512, 1024, 1536, 3072, 6144, 12288, 24576};
   static const int kCaps[] = {0, 1, 2, 4};
+  using fllf::kNtDown0, fllf::kNtDownFused, fllf::kNtUp0, fllf::kNtUp;
+  static const int kNt[] = {0, 1 << kNtUp0, (1 << kNtDownFused) | (1 << kNtUp0), (1 << kNtDown0) | (1 << kNtUp0),
+                            (1 << kNtDown0) | (1 << kNtDownFused) | (1 << kNtUp0),
+                            (1 << kNtDownFused) | (1 << kNtUp0) | (1 << kNtUp), fllf::kNtAll};
   fllf::Tuning best = ctx->tune;
   float best_ms = 0.f;
   st = timed(best, &best_ms);
   for (int p = 0; p < fllf::kTuneParams && st == FLLF_OK; ++p) {
-    if (p == fllf::kTuneGridCap && n == 1) break;  // single jobs launch one wave per work item
-    const int *cand = p == fllf::kTuneGridCap ? kCaps : kWaves;
+    if (p == fllf::kTuneGridCap && n == 1) continue;  // single jobs launch one wave per work item
+    const int *cand = p == fllf::kTuneGridCap ? kCaps : p == fllf::kTuneNtStores ? kNt : kWaves;
     const int nc = p == fllf::kTuneGridCap ? 4 : 7;
     for (int i = 0; i < nc && st == FLLF_OK; ++i) {
       if (cand[i] == best.p[p]) continue;
@@ -877,7 +885,9 @@ fllf_status fourier_llf_autotune_cached(fllf_ctx *ctx, const fllf_job *jobs, int
     while (!found && std::fgets(line, sizeof(line), f)) {
       char k[32];
       int v[fllf::kTuneParams];
-      if (std::sscanf(line, "%31s %d %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3], &v[4]) == 1 + fllf::kTuneParams &&
+      static_assert(fllf::kTuneParams == 6, "the cache line format lists every parameter");
+      if (std::sscanf(line, "%31s %d %d %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) ==
+              1 + fllf::kTuneParams &&
           std::strcmp(k, key) == 0) {
         for (int i = 0; i < fllf::kTuneParams; ++i) p[i] = v[i];
         found = true;
@@ -899,8 +909,8 @@ fllf_status fourier_llf_autotune_cached(fllf_ctx *ctx, const fllf_job *jobs, int
   FILE *f = std::fopen(cache_path, "a");
   if (!f) return fail(ctx, FLLF_EINVAL, "autotune_cached: cannot append to %s", cache_path);
   char line[128];
-  const int len = std::snprintf(line, sizeof(line), "%s %d %d %d %d %d\n", key, best[0], best[1], best[2], best[3],
-                                best[4]);
+  const int len = std::snprintf(line, sizeof(line), "%s %d %d %d %d %d %d\n", key, best[0], best[1], best[2],
+                                best[3], best[4], best[5]);
   const bool ok = std::fwrite(line, 1, (size_t)len, f) == (size_t)len;
   if (std::fclose(f) != 0 || !ok) return fail(ctx, FLLF_EINVAL, "autotune_cached: cannot write %s", cache_path);
   return FLLF_OK;

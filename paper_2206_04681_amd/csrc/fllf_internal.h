@@ -138,8 +138,12 @@ extern const char *const kHalfNames[kMaxLevels];  // "half_l<l>": re-parameteris
 // Launch-shape parameters.  waves[i] is the number of waves a pass aims for when
 // it picks its segment length (the kinds: 0 = down(0), 1 = down(l >= 1),
 // 2 = up(0), 3 = up(l >= 1)); grid_cap > 0 caps a batched launch at grid_cap
-// times the blocks that fit on the device at once (a persistent launch).
-enum { kTuneDown0 = 0, kTuneDown = 1, kTuneUp0 = 2, kTuneUp = 3, kTuneGridCap = 4, kTuneParams = 5 };
+// times the blocks that fit on the device at once (a persistent launch);
+// nt_stores is a bit set of pass kinds (kNt*) whose stores are non-temporal.
+enum { kTuneDown0 = 0, kTuneDown = 1, kTuneUp0 = 2, kTuneUp = 3, kTuneGridCap = 4, kTuneNtStores = 5, kTuneParams = 6 };
+// Bits of the non-temporal-store parameter: the pass kinds whose stores skip
+// cache reuse.
+enum { kNtDown0 = 0, kNtDownFused = 1, kNtDown = 2, kNtUp0 = 3, kNtUp = 4, kNtAll = 31 };
 struct Tuning {
   int p[kTuneParams];
 };

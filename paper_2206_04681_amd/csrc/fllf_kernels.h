@@ -65,10 +65,13 @@ __device__ inline uint32_t opaque(uint32_t v) {
   return v;
 }
 
+// Stores through a Plane made with nt = true are non-temporal (the nt cache
+// policy: the line is not kept for reuse); nt is wave-uniform.
 struct Plane {
   __amdgpu_buffer_rsrc_t r;
-  __device__ explicit Plane(const void *base)
-      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, 0x00020000)) {}
+  bool nt;
+  __device__ explicit Plane(const void *base, bool nt_ = false)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, 0x00020000)), nt(nt_) {}
   __device__ inline float ld1(uint32_t voff, uint32_t soff) const {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, sgpr(soff), 0));
   }
@@ -81,16 +84,27 @@ struct Plane {
   __device__ inline float2 ld2(uint32_t voff, uint32_t soff) const {
     return make_float2(ld1(voff, soff), ld1(voff + 4u, soff));
   }
-  __device__ inline void st1(float x, uint32_t voff, uint32_t soff) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, voff, sgpr(soff), 0);
-  }
   __device__ inline void stu(uint32_t x, uint32_t voff, uint32_t soff) const {
-    __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, sgpr(soff), 0);
+    if (nt) __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, sgpr(soff), 2);
+    else __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, sgpr(soff), 0);
+  }
+  __device__ inline void st1(float x, uint32_t voff, uint32_t soff) const {
+    stu(__builtin_bit_cast(uint32_t, x), voff, soff);
+  }
+  // 16 bytes as four adjacent dword stores with cache policy POL (2 = nt), which
+  // the backend merges into one buffer_store_dwordx4 (voff must be opaque()).
+  template <int POL>
+  __device__ inline void st4p(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t voff, uint32_t soff) const {
+    __builtin_amdgcn_raw_buffer_store_b32(a, r, voff, sgpr(soff), POL);
+    __builtin_amdgcn_raw_buffer_store_b32(b, r, voff + 4u, sgpr(soff), POL);
+    __builtin_amdgcn_raw_buffer_store_b32(c, r, voff + 8u, sgpr(soff), POL);
+    __builtin_amdgcn_raw_buffer_store_b32(d, r, voff + 12u, sgpr(soff), POL);
   }
   __device__ inline void st2(float2 x, uint32_t voff, uint32_t soff) const {
     typedef uint32_t u2 __attribute__((ext_vector_type(2)));
     const u2 v = {__builtin_bit_cast(uint32_t, x.x), __builtin_bit_cast(uint32_t, x.y)};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, sgpr(soff), 0);
+    if (nt) __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, sgpr(soff), 2);
+    else __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, sgpr(soff), 0);
   }
 };
 
@@ -155,7 +169,8 @@ __device__ inline void st_record(const Plane &p, uint32_t voff, uint32_t soff, i
 }
 
 // Stores the records of the wave's writer lanes (lanes FIRST .. FIRST + nw - 1,
-// NR dwords each, NR a multiple of 4) to one contiguous run starting at `row`.  The
+// NR dwords each, NR a multiple of 4) to one contiguous run starting at byte
+// voff0 of row soff of the record plane p (non-temporal stores when p.nt).  The
 // records go through the wave's LDS slice (lane L's record at L * (NR + 4)
 // dwords; the pad spreads the lanes over the LDS banks) so that every store
 // instruction writes 64 consecutive 16-byte pieces (whole cache lines) instead
@@ -165,28 +180,35 @@ __device__ inline void st_record(const Plane &p, uint32_t voff, uint32_t soff, i
 template <int NR>
 constexpr int staged_slice_dwords() { return 64 * (NR + 4); }
 
-template <int NR, int FIRST = 1>
-__device__ inline void st_records_staged(char *row, int lane, int nw, const uint32_t *d, uint32_t *slice) {
-  static_assert(NR % 4 == 0, "records must be whole 16-byte pieces");
+template <int NR, int FIRST, int POL>
+__device__ inline void st_staged_pieces(const Plane &p, uint32_t soff, uint32_t voff0, int lane, int total,
+                                        const uint32_t *slice) {
   constexpr int PIECES = NR / 4, STRIDE = NR + 4, ITER = (62 * PIECES + 63) / 64;
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int q = 0; q < ITER; ++q) {
+    const int t = min(q * 64 + lane, total - 1);
+    const int r = t / PIECES + FIRST, part = t - (r - FIRST) * PIECES;
+    const u4 v = *reinterpret_cast<const u4 *>(slice + r * STRIDE + 4 * part);
+    if (q * 64 + lane < total) p.st4p<POL>(v.x, v.y, v.z, v.w, opaque(voff0 + 16u * (uint32_t)t), soff);
+  }
+}
+
+template <int NR, int FIRST = 1>
+__device__ inline void st_records_staged(const Plane &p, uint32_t soff, uint32_t voff0, int lane, int nw,
+                                         const uint32_t *d, uint32_t *slice) {
+  static_assert(NR % 4 == 0, "records must be whole 16-byte pieces");
+  constexpr int PIECES = NR / 4, STRIDE = NR + 4;
 #pragma unroll
   for (int i = 0; i < PIECES; ++i)
     *reinterpret_cast<uint4 *>(slice + lane * STRIDE + 4 * i) =
         make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const int total = nw * PIECES;  // 16-byte pieces to store, record of lane FIRST first
-  // an explicitly global pointer: plain global_store_dwordx4 (not flat) even
-  // when the record plane's base was loaded from memory
-  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-  typedef __attribute__((address_space(1))) u4 gu4;
-  gu4 *dst = (gu4 *)row;
-#pragma unroll
-  for (int q = 0; q < ITER; ++q) {
-    const int t = min(q * 64 + lane, total - 1);
-    const int r = t / PIECES + FIRST, part = t - (r - FIRST) * PIECES;
-    const u4 v = *reinterpret_cast<const u4 *>(slice + r * STRIDE + 4 * part);
-    if (q * 64 + lane < total) dst[t] = v;
-  }
+  // two loops whose stores differ in their cache-policy immediate (a runtime
+  // choice between two otherwise equal stores would be merged into one)
+  if (p.nt) st_staged_pieces<NR, FIRST, 2>(p, soff, voff0, lane, total, slice);
+  else st_staged_pieces<NR, FIRST, 0>(p, soff, voff0, lane, total, slice);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
@@ -392,6 +414,7 @@ struct Geom {
   int nstrips, nsegs;  // column strips (62 coarse columns each) and row segments
   int S;               // coarse rows per segment
   int C;               // channels
+  int nt;              // 1: the pass's stores are non-temporal
 };
 
 struct DownArgs {
@@ -677,7 +700,7 @@ struct DownWave {
         }
       }
       if (writer) {
-        const Plane ap(a.af + (size_t)c * a.af_cs);
+        const Plane ap(a.af + (size_t)c * a.af_cs, a.g.nt);
         const uint32_t so = (uint32_t)r * (uint32_t)a.g.pf * 4u;
         if (two) ap.st2(make_float2(acc0, acc1), vx, so);
         else ap.st1(acc0, vx, so);
@@ -723,7 +746,7 @@ struct DownWave {
       A0 = fmaf(-m0, acc0, b0);
       A1 = fmaf(-m1, acc1, b1);
       if (!FUSE && writer) {  // this lane owns fine columns x0, x0+1
-        const Plane ap(a.af + (size_t)c * a.af_cs);
+        const Plane ap(a.af + (size_t)c * a.af_cs, a.g.nt);
         const uint32_t so = (uint32_t)r * (uint32_t)a.g.pf * 4u;
         if (two) ap.st2(make_float2(A0, A1), vx, so);
         else ap.st1(A0, vx, so);
@@ -739,9 +762,9 @@ struct DownWave {
     if (ROLE == 4 && ci >= i0 && (!FUSE || ci < i1)) {  // wave-uniform
       const uint32_t so = (uint32_t)ci * (uint32_t)a.g.pc;
       if (writer) {
-        Plane(a.gc + (size_t)c * a.gc_cs).st1(og, vcj, so * 4u);
-        if (MAP && a.mc && c == 0) Plane(a.mc).st1(om, vcj, so * 4u);
-        if (MAP && a.sc && c == 0) Plane(a.sc).st1(oq, vcj, so * 4u);
+        Plane(a.gc + (size_t)c * a.gc_cs, a.g.nt).st1(og, vcj, so * 4u);
+        if (MAP && a.mc && c == 0) Plane(a.mc, a.g.nt).st1(om, vcj, so * 4u);
+        if (MAP && a.sc && c == 0) Plane(a.sc, a.g.nt).st1(oq, vcj, so * 4u);
       }
       uint32_t q[NR];
 #pragma unroll
@@ -752,10 +775,9 @@ struct DownWave {
           PS::pack(w * oc[k], w * os[k], &q[k * DW]);
         }
       }
-      const Plane cp(a.csc + (size_t)c * a.csc_cs);
+      const Plane cp(a.csc + (size_t)c * a.csc_cs, a.g.nt);
       if (STAGED) {
-        char *row = reinterpret_cast<char *>(a.csc + (size_t)c * a.csc_cs) + (size_t)so * rec + vrun;
-        st_records_staged<NR, HL>(row, lane, nw, q, slice);
+        st_records_staged<NR, HL>(cp, so * rec, vrun, lane, nw, q, slice);
       } else if (writer) {
         st_record<NR, EX>(cp, opaque(vpcj), so * rec, nr, q);
       }
@@ -839,7 +861,7 @@ struct DownWave {
       asm volatile("" : "+v"(o[p]));  // keeps the arithmetic next to its lane shifts
     }
     if (!writer) return;
-    const Plane op(a.af + (size_t)c * a.af_cs);
+    const Plane op(a.af + (size_t)c * a.af_cs, a.g.nt);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int r = 2 * ci - 2 + q;
@@ -971,7 +993,7 @@ struct CollapseWave {
     float Dm = load_c(i0 - 1), D0 = load_c(i0), Dp = load_c(i0 + 1);
     float fa[4], fb[4];
     load_f<BORDER>(fa, i0);
-    const Plane op(outp);
+    const Plane op(outp, a.g.nt);
     const float scl[4] = {1.f / 64.f, 1.f / 16.f, 1.f / 16.f, 1.f / 4.f};
     for (int i = i0; i < i1; ++i) {
       const float Dn = load_c(i + 2);
@@ -1227,7 +1249,7 @@ struct UpWave {
       for (int k = 0; k < KM; ++k)
         if (EX || k < K) { const float2 v = term(t1.q, k); C0[k] = v.x; S0[k] = v.y; }
     }
-    const Plane op(outp);
+    const Plane op(outp, a.g.nt);
     for (int i = i0; i < i1; ++i) {
       const bool more = i + 1 < i1;  // wave-uniform: the next rows are needed
       if (more) load_c<BORDER>(rn, i + 2);
@@ -1412,6 +1434,7 @@ inline Geom make_geom(const Level &f, const Level &cl, int C, int S, int sw) {
   g.S = S;
   g.nsegs = (cl.h + S - 1) / S;
   g.C = C;
+  g.nt = 0;
   return g;
 }
 
@@ -1467,7 +1490,11 @@ inline Geom pass_geom(const JobPlan &P, int l, bool down, const Tuning &tu, bool
   const int sw = down && fused_level(P, l) ? 60 : 62;
   int S = pick_segment(P.lv[l + 1], P.C, target, sw);
   if (!down && l == 0 && !reparam && S < kUp0MinSegment) S = kUp0MinSegment;
-  return make_geom(P.lv[l], P.lv[l + 1], P.C, S, sw);
+  Geom g = make_geom(P.lv[l], P.lv[l + 1], P.C, S, sw);
+  // non-temporal stores by pass kind (bits of the tuning parameter)
+  const int bit = down ? (l == 0 ? kNtDown0 : fused_level(P, l) ? kNtDownFused : kNtDown) : (l == 0 ? kNtUp0 : kNtUp);
+  g.nt = (tu.p[kTuneNtStores] >> bit) & 1;
+  return g;
 }
 
 // Launch shape of a single-job pass: blocks of four waves, or of one wave when

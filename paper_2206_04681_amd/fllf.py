@@ -38,8 +38,8 @@ EXPORTED = ("fourier_llf_create", "fourier_llf_workspace_size", "fourier_llf_run
 # Launch-shape parameters (FLLF_TUNE_*): target waves of the REDUCE pass from
 # level 0 and from levels >= 1, of the up passes that evaluate the product-sum
 # (not the re-parameterised ones), and of the one-plane collapse of the fused
-# levels; then the grid cap.
-TUNE_NAMES = ("down0", "down", "up0", "up", "grid_cap")
+# levels; then the grid cap and the pass kinds with non-temporal stores (bits).
+TUNE_NAMES = ("down0", "down", "up0", "up", "grid_cap", "nt_stores")
 
 
 class FourierLLFError(RuntimeError):

@@ -97,7 +97,7 @@ def test_persistent_grid_cap(torch_dev, cap):
     for o in outs:
         o.fill_(-1.0)
     # few waves per pass: every wave walks many work items
-    ctx.set_tuning([0, 0, 0, 0, cap])
+    ctx.set_tuning([0, 0, 0, 0, cap, -1])
     assert ctx.get_tuning()[4] == cap
     ctx.run_jobs(fjobs)
     torch.cuda.synchronize()
@@ -160,6 +160,7 @@ def test_autotune_keeps_results(torch_dev):
     assert chosen == ctx.get_tuning()
     assert all(v in (512, 1024, 1536, 3072, 6144, 12288, 24576) for v in chosen[:4])
     assert chosen[4] in (0, 1, 2, 4)
+    assert 0 <= chosen[5] <= 31
     ctx.run_jobs(fjobs)
     torch.cuda.synchronize()
     for a, b in zip(before, outs):
@@ -181,8 +182,8 @@ def test_autotune_cache_round_trip(torch_dev, tmp_path):
     # an entry written by hand is honoured; lines that are not entries are skipped
     key = open(path).read().split()[0]
     with open(path, "w") as f:
-        f.write("# launch shapes\nnot an entry\n" + f"{key} 1024 2048 3072 6144 2\n")
-    assert ctx.autotune(fjobs, reps=1, cache=path) == [1024, 2048, 3072, 6144, 2]
+        f.write("# launch shapes\nnot an entry\n" + f"{key} 1024 2048 3072 6144 2 9\n")
+    assert ctx.autotune(fjobs, reps=1, cache=path) == [1024, 2048, 3072, 6144, 2, 9]
     # another job set has another key: timed and appended
     other = ctx.autotune(fjobs[:3], reps=1, cache=path)
     assert len(open(path).read().strip().splitlines()) == 4 and other == ctx.get_tuning()
@@ -265,7 +266,7 @@ def test_results_do_not_depend_on_the_launch_shape(torch_dev):
     first = [o.clone() for o in outs]
     for o in outs:
         o.fill_(-3.0)
-    ctx.set_tuning([512, 24576, 512, 512, 0])
+    ctx.set_tuning([512, 24576, 512, 512, 0, 31 - ctx.get_tuning()[5]])  # the other store policy too
     ctx.run_jobs(fjobs)
     torch.cuda.synchronize()
     ctx.set_tuning(None)
