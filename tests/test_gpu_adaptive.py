@@ -84,8 +84,8 @@ def test_sigma_and_boost_maps_together(torch_dev):
 
 @pytest.mark.parametrize("storage,K", [("f32", 8), ("f16", 8), ("bf16", 16)])
 def test_sigma_map_at_fused_size_every_channel(torch_dev, storage, K):
-    # 1100 x 1500 RGB: levels 1 and 2 above 2^20 samples over the channels (fused
-    # down passes, the level-1 collapse folded into up(0))
+    # 1100 x 1500 RGB: level 1 (550 x 750 x 3 channels) above the fusion threshold
+    # of 2^19 samples (fused down(1), the level-1 collapse folded into up(0))
     h, w, L = 1100, 1500, 7
     img = synth_image(h, w, 3, seed=31, n_rect=20, n_disk=20, noise=0.01)
     smap = sigma_field(h, w, seed=32)

@@ -52,7 +52,7 @@ def test_uhd_rgb_against_oracle(uhd, storage, K):
 
 
 # Fused levels at odd sizes: 2730x2186 RGB has levels 1 (1365x1093) and 2
-# (683x547) above 2^20 samples over its channels, both odd in both directions,
+# (683x547) above 2^19 samples over its channels, both odd in both directions,
 # so the fused down pass meets ragged strips and the EXPAND folds at the right
 # and bottom edges; level 3 and up keep the separate passes.
 ODD = (3, 2186, 2730)

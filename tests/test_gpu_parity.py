@@ -194,7 +194,7 @@ def test_fused_level1_shallow_pyramids(torch_dev, L):
 @pytest.mark.parametrize("h,w", [(65536, 4), (4, 65536)])
 def test_fused_levels_on_thin_images(torch_dev, h, w):
     """16 channels, 4 samples across at the 65536-sample side limit: level 1 is
-    2 wide with exactly 2^20 samples over the channels (so fused) and level 2
+    2 wide with 2^20 samples over the channels (fused: at least 2^19) and level 2
     one sample: the fused level-1 pass with one strip or over a thousand, the
     folded collapse reading a one-sample level 2.  Every channel against the oracle."""
     img = _img(h, w, c=16, seed=h % 97 + w % 89)

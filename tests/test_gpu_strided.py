@@ -38,7 +38,7 @@ def _dense(torch, x, **kw):
 
 
 # (big C, H, W), crop origin (y, x), crop (h, w), levels, K, storage.  The first
-# crop's level 1 (700 x 550 x 3 channels) is above 2^20 samples: fused down(1) and
+# crop's level 1 (700 x 550 x 3 channels) is above 2^19 samples: fused down(1) and
 # up(0) with the level-1 collapse folded in, on an odd input row pitch.
 CROPS = [((3, 1432, 1111), (17, 5), (1400, 1100), 6, 8, "f32"),
          ((3, 300, 257), (3, 1), (201, 130), 5, 4, "f32"),
