@@ -126,6 +126,11 @@ template <> struct PairStore<FLLF_STORE_F32> {
   }
 };
 
+// The 16-bit forms pack a pair with one conversion of two floats (round to
+// nearest even), C in the low half and S in the high half.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
+
 template <> struct PairStore<FLLF_STORE_F16> {
   static constexpr int DW = 1;
   __device__ static inline float2 cvt(const uint32_t *d) {
@@ -134,23 +139,20 @@ template <> struct PairStore<FLLF_STORE_F16> {
     return make_float2((float)lo, (float)hi);
   }
   __device__ static inline void pack(float c, float s, uint32_t *d) {
-    const uint16_t lo = __builtin_bit_cast(uint16_t, (_Float16)c);
-    const uint16_t hi = __builtin_bit_cast(uint16_t, (_Float16)s);
-    d[0] = (uint32_t)lo | ((uint32_t)hi << 16);
+    const half2_t v = {(_Float16)c, (_Float16)s};
+    d[0] = __builtin_bit_cast(uint32_t, v);
   }
 };
 
 template <> struct PairStore<FLLF_STORE_BF16> {
   static constexpr int DW = 1;
-  __device__ static inline uint32_t to_bf16(float f) {  // round to nearest even; finite inputs
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
-  }
   __device__ static inline float2 cvt(const uint32_t *d) {
     return make_float2(__uint_as_float(d[0] << 16), __uint_as_float(d[0] & 0xffff0000u));
   }
-  __device__ static inline void pack(float c, float s, uint32_t *d) { d[0] = to_bf16(c) | (to_bf16(s) << 16); }
+  __device__ static inline void pack(float c, float s, uint32_t *d) {
+    const bf162_t v = {(__bf16)c, (__bf16)s};
+    d[0] = __builtin_bit_cast(uint32_t, v);
+  }
 };
 
 // One pixel record: the first n dwords (n = K * DW) at voff; adjacent dword
