@@ -537,6 +537,12 @@ struct DownWave {
   // halo lanes a side, so that the coarse values EXPAND needs (lanes 1 .. 62)
   // are exact.  Otherwise levels >= 1 store the level-l half A_l only.
   static constexpr int SW = FUSE ? 60 : 62;  // coarse columns per strip
+  // Level 0 of the 16-bit forms, which is bound by its ALU work, reads the two
+  // input columns of a lane as two 4-byte loads (at their folded offsets, the
+  // columns themselves on interior strips) rather than one 8-byte load: 4K RGB
+  // K=8 down(0) float16 83.8 -> 81.7 us, bfloat16 84.1 -> 81.3 us (float32,
+  // bound by its traffic, 104.7 -> 106.2 us keeps the 8-byte load).
+  static constexpr bool SPLIT2 = L0 && ST != FLLF_STORE_F32;
   static constexpr int HL = FUSE ? 2 : 1;    // halo lanes on each side
   const DownArgs &a;
   int c, K, nr, j, i0, i1, x0, lane, nw;
@@ -595,7 +601,7 @@ struct DownWave {
   // border strips, one contiguous 8-byte access otherwise.
   template <bool BORDER>
   __device__ inline void ld_f2(const Plane &p, uint32_t soff, float &x, float &y) const {
-    if (BORDER) {
+    if (BORDER || SPLIT2) {
       x = p.ld1(vf0, soff);
       y = p.ld1(vf1, soff);
     } else {
@@ -1083,15 +1089,14 @@ struct UpWave {
   struct FBlk {  // fine 2x2 block as loaded: G (or I), A (or I), boost, range scale
     float g[4], b[4], m[4], s[4];
   };
-  // interior strips read each coarse row of records as one coalesced span
-  static constexpr bool SPAN = EX;
-  static constexpr int SLICE = SPAN ? span_slice_dwords<NR>() : 1;
+  // Each lane loads its own records (16-byte loads).  Unlike the down passes,
+  // the up passes read them faster this way than as a coalesced span
+  // transposed through LDS (4K RGB K=8 up(0): float32 133.5 -> 132 us,
+  // float16 93 -> 92 us).
   const UpArgs &a;
   int c, K, nr, j, i0, i1, x0, lane;
   bool writer, two, border, vec_f;
   uint32_t rec, vcj, vpcj, vx, vxa, vxb;  // record bytes, lane byte offsets
-  uint32_t vspan;                         // record offset of lane 0's coarse column
-  uint32_t *slice;                        // this wave's LDS slice
   const float *gc, *oc, *base, *gfp;
   const uint32_t *csc;
   float *outp;
@@ -1099,10 +1104,9 @@ struct UpWave {
   uint32_t vq[3];     // FOLD: byte offsets of the level-2 columns q-1, q, q+1 (folded)
   float wx[3];        // FOLD: their EXPAND weights at the lane's level-1 column
 
-  __device__ UpWave(const UpArgs &args, int lane_, int c_, int strip, int seg, uint32_t *slice_) : a(args) {
+  __device__ UpWave(const UpArgs &args, int lane_, int c_, int strip, int seg) : a(args) {
     const Geom &g = a.g;
     lane = lane_;
-    slice = slice_;
     c = c_;
     K = EX ? KM : a.cf.K;
     nr = K * DW;
@@ -1115,7 +1119,6 @@ struct UpWave {
     i1 = min(i0 + g.S, g.Hc);
     writer = lane >= 1 && lane <= 62 && j < g.Wc;
     border = sgpr(border_strip(strip, g.Wf));  // uniform
-    vspan = border ? 0u : (uint32_t)(strip * 62 - 1) * rec;
     x0 = 2 * j;
     two = x0 + 1 < g.Wf;
     // border waves read clamped columns (values of non-writer lanes are unused)
@@ -1160,13 +1163,7 @@ struct UpWave {
         for (int dx = 0; dx < 3; ++dx) d.e[3 * dy + dx] = p2.ld1(vq[dx], ro);
       }
     }
-    if (SPAN && !BORDER) ld_span<NR>(Plane(csc), ci * rec + vspan, lane, d.q);  // transposed before use
-    else ld_record<NR, EX>(Plane(csc), opaque(vpcj), ci * rec, nr, d.q);
-  }
-
-  template <bool BORDER>
-  __device__ inline void ready(CRow &d) {
-    if (SPAN && !BORDER) transpose_span<NR>(d.q, slice, lane);
+    ld_record<NR, EX>(Plane(csc), opaque(vpcj), ci * rec, nr, d.q);
   }
 
   // O_{l+1} - G_{l+1} at a coarse sample (FOLD: the level-1 collapse, on the fly;
@@ -1240,12 +1237,10 @@ struct UpWave {
       load_c<BORDER>(t1, i0);
       load_c<BORDER>(rp, i0 + 1);
       load_f<BORDER>(fa, i0);
-      ready<BORDER>(t0);
       if (HASD) Dm = dval(t0);
 #pragma unroll
       for (int k = 0; k < KM; ++k)
         if (EX || k < K) { const float2 v = term(t0.q, k); Cm[k] = v.x; Sm[k] = v.y; }
-      ready<BORDER>(t1);
       if (HASD) D0 = dval(t1);
 #pragma unroll
       for (int k = 0; k < KM; ++k)
@@ -1255,7 +1250,6 @@ struct UpWave {
     for (int i = i0; i < i1; ++i) {
       const bool more = i + 1 < i1;  // wave-uniform: the next rows are needed
       if (more) load_c<BORDER>(rn, i + 2);
-      ready<BORDER>(rp);
       if (more) load_f<BORDER>(fb, i + 1);
       const float Dp = HASD ? dval(rp) : 0.f;
       float ED[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1347,10 +1341,9 @@ template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool RW = false
           bool FAST = false>
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM)) up_kernel(UpArgs a) {
   using W = UpWave<ST, KM, EX, L0, MAP, HASD, RW, FOLD, FAST>;
-  __shared__ __attribute__((aligned(16))) uint32_t stage[4 * W::SLICE];
   int lane, strip, seg, c;
   if (!wave_coords(a.g, lane, strip, seg, c)) return;  // uniform per wave
-  W w(a, lane, c, strip, seg, stage + (threadIdx.x >> 6) * W::SLICE);
+  W w(a, lane, c, strip, seg);
   w.run();
 }
 
@@ -1358,7 +1351,6 @@ template <int ST, int KM, bool EX, bool L0, bool MAP, bool HASD, bool FOLD = fal
 __global__ void __launch_bounds__(256, min_waves_per_simd(KM))
 up_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restrict__ start, int n, uint32_t total) {
   using W = UpWave<ST, KM, EX, L0, MAP, HASD, false, FOLD>;
-  __shared__ __attribute__((aligned(16))) uint32_t stage[4 * W::SLICE];
   const int lane = threadIdx.x & 63;
   const uint32_t stride = gridDim.x * 4u;
   for (uint32_t w = first_wave(); w < total; w += stride) {
@@ -1366,7 +1358,7 @@ up_batch_kernel(const UpArgs *__restrict__ jobs, const uint32_t *__restrict__ st
     const UpArgs &a = jobs[j];
     int strip, seg, c;
     job_coords(a.g, w - start[j], strip, seg, c);
-    W wv(a, lane, c, strip, seg, stage + (threadIdx.x >> 6) * W::SLICE);
+    W wv(a, lane, c, strip, seg);
     wv.run();
   }
 }
