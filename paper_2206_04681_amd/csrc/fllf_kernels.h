@@ -237,8 +237,24 @@ __device__ inline void ld_span(const Plane &p, uint32_t soff, int lane, uint32_t
   }
 }
 
+// A run whose first n 16-byte chunks only are in bounds (a border strip's
+// row): chunks past n load chunk n - 1 again; their values are never picked.
 template <int D>
-__device__ inline void transpose_span(uint32_t *q, uint32_t *slice, int lane) {
+__device__ inline void ld_span_n(const Plane &p, uint32_t soff, int lane, uint32_t n, uint32_t *q) {
+  static_assert(D % 4 == 0, "whole 16-byte chunks");
+  const uint32_t last = 16u * (n - 1u);
+#pragma unroll
+  for (int c = 0; c < D / 4; ++c) {
+    const uint32_t v = opaque(min(16u * (uint32_t)(64 * c + lane), last));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) q[4 * c + e] = p.ldu(v + 4u * e, soff);
+  }
+}
+
+// The chunks go to LDS at their place in the span: slot u holds dwords
+// u D .. u D + D - 1 of the span, followed by 4 pad dwords.
+template <int D>
+__device__ inline void span_to_slice(const uint32_t *q, uint32_t *slice, int lane) {
   typedef uint32_t u4 __attribute__((ext_vector_type(4)));
   constexpr int LD = D + 4;  // LDS dwords per lane
 #pragma unroll
@@ -248,6 +264,29 @@ __device__ inline void transpose_span(uint32_t *q, uint32_t *slice, int lane) {
     *reinterpret_cast<u4 *>(slice + u * LD + off) = u4{q[4 * c], q[4 * c + 1], q[4 * c + 2], q[4 * c + 3]};
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Border strips: lane t takes its two records of R dwords (the span holds two
+// per slot) from slice dword offsets o0 and o1, those of its folded columns.
+template <int R>
+__device__ inline void transpose_span_pick(uint32_t *q, uint32_t *slice, int lane, uint32_t o0, uint32_t o1) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  span_to_slice<2 * R>(q, slice, lane);
+#pragma unroll
+  for (int c = 0; c < R / 4; ++c) {
+    const u4 v = *reinterpret_cast<const u4 *>(slice + o0 + 4 * c);
+    const u4 w = *reinterpret_cast<const u4 *>(slice + o1 + 4 * c);
+    q[4 * c] = v.x; q[4 * c + 1] = v.y; q[4 * c + 2] = v.z; q[4 * c + 3] = v.w;
+    q[R + 4 * c] = w.x; q[R + 4 * c + 1] = w.y; q[R + 4 * c + 2] = w.z; q[R + 4 * c + 3] = w.w;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+template <int D>
+__device__ inline void transpose_span(uint32_t *q, uint32_t *slice, int lane) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  constexpr int LD = D + 4;  // LDS dwords per lane
+  span_to_slice<D>(q, slice, lane);
 #pragma unroll
   for (int c = 0; c < D / 4; ++c) {
     const u4 v = *reinterpret_cast<const u4 *>(slice + lane * LD + 4 * c);
@@ -552,6 +591,20 @@ struct DownWave {
   uint32_t vrun;                                       // record offset of the first writer lane's coarse column
   uint32_t vspan;                                      // record offset of lane 0's fine column x0
   uint32_t *slice;                                     // this wave's LDS staging slice
+  // Border strips of the fused (large-level) passes read the in-bounds part of
+  // each row's run of records as a span as well, and every lane picks the
+  // records of its folded columns from the slice: per-lane record loads touch
+  // 64 cache lines per instruction against 8, and made the border waves the
+  // last to finish (4K RGB float32 down(1): 119 us, 106 us with those waves
+  // idle, 113.5 us with spans).  On the small levels, bound by latency, the
+  // slice round trip costs more than it saves, so they keep per-lane loads.
+  // With at least 6 in-bounds fine columns, the folded columns of every lane
+  // that feeds a writer (two lanes past the last one, whose columns fold back
+  // at most 6 from the edge) lie in the span; narrower strips load per lane.
+  static constexpr bool BSPAN = SPAN && FUSE;
+  bool bspan;
+  uint32_t bchunks;       // in-bounds 16-byte chunks of the span
+  uint32_t boff0, boff1;  // slice dword offsets of the lane's two records
   const float *gf;
   const uint32_t *csf;
   float PG0, PG1, PM0, PM1, PQ0, PQ1;
@@ -593,6 +646,21 @@ struct DownWave {
     vpf1 = (uint32_t)f1 * rec;
     vcj = (uint32_t)max(j, 0) * 4u;
     vpcj = (uint32_t)max(j, 0) * rec;
+    bspan = false;
+    bchunks = 0u;
+    boff0 = boff1 = 0u;
+    if (BSPAN && border) {
+      const int c0 = 2 * (strip * SW - HL);  // fine column of lane 0's first record
+      const int s0 = max(c0, 0), cnt = min(c0 + 128, a.g.Wf) - s0;  // wave-uniform
+      if (cnt >= 6) {
+        bspan = true;
+        vspan = (uint32_t)s0 * rec;
+        bchunks = (uint32_t)(cnt * NR / 4);
+        const int r0 = min(max(f0 - s0, 0), cnt - 1), r1 = min(max(f1 - s0, 0), cnt - 1);
+        boff0 = (uint32_t)((r0 >> 1) * (2 * NR + 4) + (r0 & 1) * NR);
+        boff1 = (uint32_t)((r1 >> 1) * (2 * NR + 4) + (r1 & 1) * NR);
+      }
+    }
     gf = a.gf + (size_t)c * a.gf_cs;
     csf = L0 ? nullptr : a.csf + (size_t)c * a.csf_cs;
   }
@@ -611,7 +679,7 @@ struct DownWave {
     }
   }
 
-  template <bool BORDER>
+  template <bool BORDER, bool BS = false>
   __device__ inline void load(RowIn &d, int r) const {
     const uint32_t fr = (uint32_t)reflect(r, a.g.Hf);
     ld_f2<BORDER>(Plane(gf), fr * (uint32_t)a.g.pf * 4u, d.g0, d.g1);
@@ -625,9 +693,11 @@ struct DownWave {
     if (!L0) {
       const Plane p(csf);
       const uint32_t so = fr * (uint32_t)a.g.pf * rec;
-      if (BORDER) {
+      if (BORDER && !(SPAN && BS)) {
         ld_record<NR, EX>(p, opaque(vpf0), so, nr, d.q);
         ld_record<NR, EX>(p, opaque(vpf1), so, nr, d.q + NR);
+      } else if (SPAN && BORDER) {
+        ld_span_n<2 * NR>(p, so + vspan, lane, bchunks, d.q);  // picked before use
       } else if (SPAN) {
         ld_span<2 * NR>(p, so + vspan, lane, d.q);  // transposed before use
       } else {
@@ -638,10 +708,12 @@ struct DownWave {
     }
   }
 
-  // Interior strips: the loaded span chunks become this lane's two records.
-  template <bool BORDER>
+  // The loaded span chunks become this lane's two records (border strips: those
+  // of its folded columns).
+  template <bool BORDER, bool BS = false>
   __device__ inline void ready(RowIn &d) {
     if (SPAN && !BORDER) transpose_span<2 * NR>(d.q, slice, lane);
+    else if (SPAN && BS) transpose_span_pick<NR>(d.q, slice, lane, boff0, boff1);
   }
 
   // Consume fine row r (stream role ROLE); ROLE 4 emits coarse row ci.
@@ -885,29 +957,36 @@ struct DownWave {
   // then starts one coarse row early, and its first emission (coarse row
   // i0 - 1, incomplete) is not stored.  A single steady-state loop body keeps
   // the register peak that of one row plus the prefetched next row.
-  template <bool BORDER>
+  template <bool BORDER, bool BS = false>
   __device__ inline void stream() {
     // FUSE also needs coarse rows i0 - 1 and i1 (EXPAND halo): one coarse row
     // more on each side
     const int first = FUSE ? i0 - 2 : i0 - 1, last = FUSE ? i1 + 1 : i1;
     RowIn A, B;
-    load<BORDER>(A, 2 * first);
-    load<BORDER>(B, 2 * first + 1);
-    ready<BORDER>(A);
+    load<BORDER, BS>(A, 2 * first);
+    load<BORDER, BS>(B, 2 * first + 1);
+    ready<BORDER, BS>(A);
     process<0>(A, 2 * first, first);
     for (int i = first; i < last; ++i) {
-      load<BORDER>(A, 2 * i + 2);
-      ready<BORDER>(B);
+      load<BORDER, BS>(A, 2 * i + 2);
+      ready<BORDER, BS>(B);
       process<3>(B, 2 * i + 1, i);
-      load<BORDER>(B, 2 * i + 3);
-      ready<BORDER>(A);
+      load<BORDER, BS>(B, 2 * i + 3);
+      ready<BORDER, BS>(A);
       process<4>(A, 2 * i + 2, i);
     }
   }
 
-  // one wave-uniform branch selects the row loop of border or interior strips
+  // one wave-uniform branch selects the row loop of interior strips, of border
+  // strips read as spans, or of border strips read per lane
   __device__ inline void run() {
-    if (border) stream<true>(); else stream<false>();
+    if (!border) {
+      stream<false>();
+    } else if constexpr (BSPAN) {
+      if (bspan) stream<true, true>(); else stream<true>();
+    } else {
+      stream<true>();
+    }
   }
 };
 
