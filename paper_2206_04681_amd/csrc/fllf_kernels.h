@@ -601,7 +601,10 @@ struct DownWave {
   // With at least 6 in-bounds fine columns, the folded columns of every lane
   // that feeds a writer (two lanes past the last one, whose columns fold back
   // at most 6 from the edge) lie in the span; narrower strips load per lane.
-  static constexpr bool BSPAN = SPAN && FUSE;
+  // Loops of 16 terms keep per-lane border loads: their fused pass is at the
+  // edge of the register file, and a third row loop put its row buffers in
+  // scratch memory (float16 K=16 4K RGB: 0.64 -> 2.7 ms).
+  static constexpr bool BSPAN = SPAN && FUSE && KM <= 8;
   bool bspan;
   uint32_t bchunks;       // in-bounds 16-byte chunks of the span
   uint32_t boff0, boff1;  // slice dword offsets of the lane's two records
