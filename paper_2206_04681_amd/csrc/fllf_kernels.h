@@ -551,6 +551,10 @@ struct NoRing {};
 // Pyramid records the fused pass keeps in registers without spilling: exact
 // K loops of at most 16 dwords per record (float32 K <= 8, 16-bit K <= 16).
 constexpr bool fusable(int K, int dwp) { return (K == 4 || K == 8 || K == 16) && K * dwp <= 16; }
+// ... except 16 terms with per-pixel maps: their ring plus the maps' values
+// exceed the register file (16-bit storage: 1.5 KB per lane in scratch memory;
+// 4K RGB K=16 with a range-scale map 3.2 ms fused against 0.8 ms separate).
+constexpr bool fusable(int K, int dwp, bool map) { return fusable(K, dwp) && !(map && K == 16); }
 
 // FAST: the fast LLF comparator (Sec. II-C): the records hold the pyramids of the
 // sampled remaps r(I, tau j) (level 0: formed in registers), and the level-l
@@ -1538,7 +1542,8 @@ inline long geom_waves(const Geom &g) { return (long)g.nstrips * g.nsegs * g.C; 
 // float16 is slower.
 constexpr double kFuseMinSamples = 1 << 19;
 inline bool fused_level(const JobPlan &P, int l) {
-  return l >= 1 && !P.fast && fusable(P.K, P.dwp) && (double)P.lv[l].n * P.C >= kFuseMinSamples;
+  const bool map = P.m_map != nullptr || P.s_map != nullptr;
+  return l >= 1 && !P.fast && fusable(P.K, P.dwp, map) && (double)P.lv[l].n * P.C >= kFuseMinSamples;
 }
 
 // A fused level 1 below the top has its collapse folded into up(0), which then
@@ -1688,7 +1693,7 @@ inline double up_bytes(const JobPlan &P, int l, int dwp, bool reparam = false) {
 // selects it for the others).
 template <int ST, int KM, bool EX, bool MAP>
 void launch_fused_down(const DownArgs &a, hipStream_t st) {
-  if constexpr (EX && fusable(KM, PairStore<ST>::DW))
+  if constexpr (EX && fusable(KM, PairStore<ST>::DW, MAP))
     down_kernel<ST, KM, EX, false, MAP, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
 }
 
@@ -1696,7 +1701,7 @@ void launch_fused_down(const DownArgs &a, hipStream_t st) {
 // (fold_level1 implies a fused level 1).
 template <int ST, int KM, bool EX, bool MAP>
 void launch_fold_up(const UpArgs &a, hipStream_t st) {
-  if constexpr (EX && fusable(KM, PairStore<ST>::DW))
+  if constexpr (EX && fusable(KM, PairStore<ST>::DW, MAP))
     up_kernel<ST, KM, EX, true, MAP, true, false, true><<<grid_for(a.g), block_for(a.g), 0, st>>>(a);
 }
 
@@ -1883,7 +1888,7 @@ hipError_t launch_batch_typed(const BatchLaunch &b, char *ws, hipStream_t st, co
     if (b.l0) {
       FLLF_DOWN(true, false)
     } else if (b.fuse) {
-      if constexpr (EX && fusable(KM, PairStore<ST>::DW)) FLLF_DOWN(false, true)
+      if constexpr (EX && fusable(KM, PairStore<ST>::DW, MAP)) FLLF_DOWN(false, true)
     } else {
       FLLF_DOWN(false, false)
     }
@@ -1899,7 +1904,7 @@ hipError_t launch_batch_typed(const BatchLaunch &b, char *ws, hipStream_t st, co
     // level 0, fuse marks the jobs whose level-1 collapse is folded in
     if (b.l0) {
       if (b.fuse) {
-        if constexpr (EX && fusable(KM, PairStore<ST>::DW)) FLLF_UP(true, true, true)
+        if constexpr (EX && fusable(KM, PairStore<ST>::DW, MAP)) FLLF_UP(true, true, true)
       } else if (b.hasd) {
         FLLF_UP(true, true, false)
       } else {
