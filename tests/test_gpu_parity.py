@@ -202,3 +202,17 @@ def test_fused_levels_on_thin_images(torch_dev, h, w):
     want = oracle_channels(img, 3, 0.2, 2.0, 4)
     errs, _ = report(f"{w}x{h}, 16 channels", got, want)
     assert max(errs) <= TOL_F32
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", TOL_F32), ("f16", TOL_F16)])
+@pytest.mark.parametrize("w", [961, 963, 966])
+def test_fused_level1_last_strip_widths(torch_dev, w, storage, tol):
+    """800 x w RGB, level 1 fused: its last strip holds 5, 6 or 7 in-bounds fine
+    columns (w = 961, 963, 966), on both sides of the 6 from which a border strip
+    reads its record rows as a span and picks the folded columns (below it the
+    records are loaded per lane).  Every channel against the oracle."""
+    img = _img(800, w, c=3, seed=w)
+    got = gpu_run(torch_dev, img, 5, 0.15, 2.5, 8, storage=storage)
+    want = oracle_channels(img, 5, 0.15, 2.5, 8)
+    errs, _ = report(f"800x{w} RGB, {storage}", got, want)
+    assert max(errs) <= tol
