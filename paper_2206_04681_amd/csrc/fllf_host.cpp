@@ -185,6 +185,11 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
   p->levels = job.levels;
   p->fast = (job.flags & FLLF_FLAG_FAST_LLF) != 0;
   p->K = p->fast ? job.K / 2 : job.K;
+  // With a per-pixel map, 9 to 15 terms run the exact 16-term loop with the
+  // extra terms' weights zero (alpha~_k = 0 for k >= K below): their records are
+  // zero and add exact zeros to every sum, while the guarded 16-term loop with
+  // maps kept about 0.9 KB per lane in scratch memory.
+  if (!p->fast && (job.m_map || job.sigma_map) && job.K > 8 && job.K < 16) p->K = 16;
   p->C = job.channels;
   p->dwp = storage == FLLF_STORE_F32 ? 2 : 1;
   p->in = job.in;
@@ -260,7 +265,7 @@ void plan_job(const fllf_job &job, fllf_storage storage, size_t base, JobPlan *p
   fourier_terms(job.sigma_r, job.K, T, nullptr, at);
   p->coefs.inv_T = (float)(1.0 / T);
   p->coefs.m = (float)job.m;
-  p->coefs.K = job.K;
+  p->coefs.K = p->K;
   p->coefs.has_mmap = job.m_map ? 1 : 0;
   p->coefs.has_smap = job.sigma_map ? 1 : 0;
   p->coefs.sref = (float)job.sigma_r;

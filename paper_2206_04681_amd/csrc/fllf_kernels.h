@@ -1794,7 +1794,10 @@ hipError_t launch_storage(const JobPlan &P, char *ws, hipStream_t st, LaunchHook
     FLLF_LAUNCH(16, true);
   }
   if (km == 8) FLLF_LAUNCH(8, false);
-  if (km == 16) FLLF_LAUNCH(16, false);
+  if (km == 16) {  // with a map, 9 to 15 terms are planned as the exact 16-term loop
+    if (map) return hipErrorInvalidValue;
+    return launch_typed<ST, 16, false, false>(P, ws, st, h, tu);
+  }
   FLLF_LAUNCH(32, false);
 #undef FLLF_LAUNCH
 }
@@ -1941,7 +1944,8 @@ hipError_t launch_batch_storage(const BatchSchedule &s, char *ws, hipStream_t st
         else FLLF_B(16, true);
       } else {
         if (b.km == 8) FLLF_B(8, false);
-        else if (b.km == 16) FLLF_B(16, false);
+        else if (b.km == 16 && !b.map) e = launch_batch_typed<ST, 16, false, false>(b, ws, st, tu);
+        else if (b.km == 16) e = hipErrorInvalidValue;  // planned as the exact 16-term loop
         else FLLF_B(32, false);
       }
 #undef FLLF_B

@@ -71,6 +71,21 @@ def test_sigma_map_against_oracle(torch_dev, h, w, L, K):
     assert ref.max_abs(got[0] if got.ndim == 3 else got, want[0]) <= TOL["f32"]
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("K", [9, 12, 15])
+def test_maps_with_9_to_15_terms(torch_dev, K, storage):
+    """Both maps with 9 to 15 terms: the job runs the exact 16-term loop with the
+    extra terms' weights zero.  Every channel against the oracle with K terms."""
+    h, w, L = 150, 210, 6
+    img = synth_image(h, w, 3, seed=K)
+    smap = sigma_field(h, w, seed=K + 1, lo=0.08, hi=0.25)
+    mmap = (1.0 + 2.0 * synth_image(h, w, 1, seed=K + 2)[0]).astype(np.float32)
+    got = run_gpu(torch_dev, img, L, smap, K, m=0.0, mmap=mmap, storage=storage)
+    want = oracle(img, L, smap, K, m=0.0, mmap=mmap)
+    errs, _ = report(f"150x210 RGB, both maps, K={K}, {storage}", got, want)
+    assert max(errs) <= TOL[storage]
+
+
 def test_sigma_and_boost_maps_together(torch_dev):
     h, w, L, K = 96, 110, 5, 8
     img = synth_image(h, w, 3, seed=4)
